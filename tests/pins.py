@@ -1,0 +1,471 @@
+"""Independent pins of the CPU oracle.
+
+Each ``pin_*`` takes an ``oracle.Oracle`` and returns ``(ok, detail)``.
+None of them re-types the oracle's formulas: they compare against closed
+forms (uniform motion, Heaviside-Feynman, Coulomb, Lienard's power, dipole
+geometry, exact gyration), against brute-force root scans written with a
+different method (sign-change bisection instead of the quadratic), or
+against convergence orders on an exactly known orbit.
+
+``tests/test_oracle_pins.py`` asserts every pin on the real oracle;
+``tests/test_oracle_mutants.py`` builds oracle variants with one planted
+mistake each and asserts that at least one pin fails for every variant.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from paper_2605_05543_amd import bunch
+
+# CODATA 2018, written here independently of the oracle.
+C = 299792458.0
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+MU0 = 1.25663706212e-6
+EPS0 = 1.0 / (MU0 * C * C)
+KC = 1.0 / (4.0 * math.pi * EPS0)
+
+
+def _rel(a, b, floor=0.0):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.maximum(np.abs(b), floor)
+    return float(np.max(np.abs(a - b) / den)) if a.size else 0.0
+
+
+def _vec_rel(a, b):
+    """max over columns of |a - b| / |b| for [3, m] arrays."""
+    num = np.linalg.norm(a - b, axis=0)
+    den = np.linalg.norm(b, axis=0)
+    return float(np.max(num / den))
+
+
+# -- closed forms (test-side) ---------------------------------------------------
+
+def uniform_light_distance(R, beta):
+    """c (t - t_r) for a source in uniform motion with velocity beta*c whose
+    *present* offset to the observer is R: the positive root of
+    (1 - b^2) s^2 - 2 (R.b) s - R^2 = 0."""
+    Rb = np.einsum("i...,i...->...", R, beta)
+    R2 = np.einsum("i...,i...->...", R, R)
+    b2 = np.einsum("i...,i...->...", beta, beta)
+    return (Rb + np.sqrt(Rb * Rb + (1.0 - b2) * R2)) / (1.0 - b2)
+
+
+def heaviside_feynman(R, vel, q):
+    """Field of a charge in uniform motion, from its present offset R:
+    E = k q (1 - b^2) Rhat / (R^2 (1 - b^2 sin^2 psi)^{3/2}), B = v x E / c^2."""
+    b = vel / C
+    b2 = (b * b).sum(0)
+    Rn = np.linalg.norm(R, axis=0)
+    cospsi = (R * b).sum(0) / (Rn * np.sqrt(np.maximum(b2, 1e-300)))
+    cospsi = np.where(b2 > 0, cospsi, 0.0)
+    sin2 = 1.0 - cospsi * cospsi
+    E = KC * q * (1.0 - b2) * R / (Rn**3 * (1.0 - b2 * sin2) ** 1.5)
+    B = np.cross(vel.T, E.T).T / (C * C)
+    return E, B
+
+
+def lw_kappa_form(r, w, vel, acc, q):
+    """General Lienard-Wiechert field in the (n - beta, kappa) form:
+    E = k q [ (n - b)(1 - b^2) / (kappa^3 R^2) + n x ((n - b) x bdot) / (c kappa^3 R) ],
+    B = n x E / c, kappa = 1 - n.b.  Columns are (target, source) pairs."""
+    Rv = r - w
+    R = np.linalg.norm(Rv, axis=0)
+    n = Rv / R
+    b = vel / C
+    bd = acc / C
+    kap = 1.0 - (n * b).sum(0)
+    nb = n - b
+    b2 = (b * b).sum(0)
+    vel_term = nb * (1.0 - b2) / (kap**3 * R**2)
+    rad = np.cross(n.T, np.cross(nb.T, bd.T)).T / (C * kap**3 * R)
+    E = KC * q * (vel_term + rad)
+    B = np.cross(n.T, E.T).T / C
+    return E, B
+
+
+def circle_orbit(t, rho, om):
+    ph = om * t
+    w = np.stack([rho * np.cos(ph), rho * np.sin(ph), np.zeros_like(ph)])
+    v = np.stack([-rho * om * np.sin(ph), rho * om * np.cos(ph), np.zeros_like(ph)])
+    a = np.stack([-rho * om * om * np.cos(ph), -rho * om * om * np.sin(ph), np.zeros_like(ph)])
+    return w, v, a
+
+
+def circle_retarded_time(r, t, rho, om):
+    """Exact retarded time on the circular orbit by sign-change bisection
+    of g(s) = c (t - s) - |r - w(s)| (strictly decreasing in s)."""
+    rn = np.linalg.norm(r, axis=0)
+    lo = t - (rn + rho) / C - 1e-12
+    hi = t - np.maximum(rn - rho, 0.0) / C + 1e-12
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        w, _, _ = circle_orbit(mid, rho, om)
+        g = C * (t - mid) - np.linalg.norm(r - w, axis=0)
+        pos = g > 0
+        lo = np.where(pos, mid, lo)
+        hi = np.where(pos, hi, mid)
+    return 0.5 * (lo + hi)
+
+
+# -- pins -------------------------------------------------------------------------
+
+def pin_constants(orc):
+    ok = (orc.c == C and orc.e == QE and orc.me == ME and orc.mu0 == MU0 and abs(orc.kC / KC - 1) < 1e-15)
+    return ok, f"c={orc.c} e={orc.e} me={orc.me} mu0={orc.mu0} kC={orc.kC}"
+
+
+def _uniform_case(seed=11, ns=64, dt=1e-13, beta=0.94):
+    rng = np.random.default_rng(seed)
+    nsrc = 5
+    d = rng.standard_normal((3, nsrc))
+    d /= np.linalg.norm(d, axis=0)
+    vel = beta * C * d
+    w_now = 1e-3 * rng.standard_normal((3, nsrc))
+    T, w, v = bunch.uniform_history(ns, dt, w_now, vel)
+    x = 2e-3 * rng.standard_normal((3, 40))
+    return T, w, v, x, w_now, vel
+
+
+def pin_uniform_retarded_time(orc):
+    """Retarded time of uniformly moving sources (in history and
+    extrapolated before it) against the closed-form root."""
+    T, w, v, x, w_now, vel = _uniform_case()
+    out = orc.retarded(T, w, v, T[-1], x)
+    m, N = out["kstar"].shape
+    worst = 0.0
+    for a in range(m):
+        for j in range(N):
+            R = x[:, a] - w_now[:, j]
+            s_exact = uniform_light_distance(R, vel[:, j] / C)
+            s_or = C * (T[-1] - out["tr"][a, j])
+            worst = max(worst, abs(s_or - s_exact) / s_exact)
+    frac_before = float((out["kstar"] < 0).mean())
+    ok = worst < 1e-13 and 0.05 < frac_before < 0.95
+    return ok, f"max rel err of c(t-t_r) = {worst:.3e}; before-history fraction {frac_before:.2f}"
+
+
+def pin_heaviside_feynman(orc):
+    """Fields of uniformly moving sources against Heaviside-Feynman."""
+    T, w, v, x, w_now, vel = _uniform_case(seed=12)
+    q = -QE
+    worst_e = worst_b = 0.0
+    for j in range(w.shape[2]):
+        E, B = orc.fields(T, w[:, :, j:j + 1], v[:, :, j:j + 1], q, T[-1], x)
+        Eh, Bh = heaviside_feynman(x - w_now[:, j:j + 1], vel[:, j:j + 1], q)
+        worst_e = max(worst_e, _vec_rel(E, Eh))
+        worst_b = max(worst_b, _vec_rel(B, Bh))
+    ok = worst_e < 1e-12 and worst_b < 1e-12
+    return ok, f"HF max rel err E {worst_e:.3e} B {worst_b:.3e}"
+
+
+def pin_coulomb(orc):
+    """A source at rest gives k q Rhat / R^2 and no magnetic field."""
+    rng = np.random.default_rng(13)
+    T, w, v = bunch.uniform_history(32, 1e-13, rng.standard_normal((3, 1)) * 1e-3, np.zeros((3, 1)))
+    x = 1e-3 * rng.standard_normal((3, 30))
+    E, B = orc.fields(T, w, v, QE, T[-1], x)
+    R = x - w[-1]
+    Eh = KC * QE * R / np.linalg.norm(R, axis=0) ** 3
+    err = _vec_rel(E, Eh)
+    # B = eta_hat x E / c vanishes up to the rounding of E's direction
+    bmax = float(np.max(np.linalg.norm(B, axis=0) * C / np.linalg.norm(E, axis=0)))
+    return err < 1e-14 and bmax < 1e-15, f"Coulomb rel err {err:.3e}; max c|B|/|E| {bmax:.3e}"
+
+
+def pin_before_history_field(orc):
+    """Pairs whose retarded time precedes the stored history must see the
+    field of a charge coasting with the oldest stored velocity (the
+    extrapolation with zero acceleration), i.e. Heaviside-Feynman about the
+    coasting charge's present position w_0 + v_0 (t - T_0)."""
+    T, w, v = bunch.wiggly_history(4, 24, 1e-13, beta=0.9, accel_rel=0.2, seed=21)
+    rng = np.random.default_rng(22)
+    x = 3e-3 * rng.standard_normal((3, 60))
+    ks = orc.retarded(T, w, v, T[-1], x)["kstar"]
+    worst = 0.0
+    count = 0
+    for j in range(w.shape[2]):
+        sel = np.nonzero(ks[:, j] < 0)[0]
+        if sel.size == 0:
+            continue
+        count += sel.size
+        E, _ = orc.fields(T, w[:, :, j:j + 1], v[:, :, j:j + 1], -QE, T[-1], x[:, sel])
+        w_virtual = w[0, :, j:j + 1] + v[0, :, j:j + 1] * (T[-1] - T[0])
+        Eh, _ = heaviside_feynman(x[:, sel] - w_virtual, v[0, :, j:j + 1], -QE)
+        worst = max(worst, _vec_rel(E, Eh))
+    return count > 20 and worst < 1e-11, f"{count} before-history pairs, max rel err {worst:.3e}"
+
+
+def _segment_root_bisect(r, t, T, w, v, k, j, lo, hi):
+    """Root of g(d) = c (t - T_k - d) - |r - w_k - v_k d| on [lo, hi] by
+    bisection (no quadratic formula)."""
+    def g(dd):
+        p = w[k, :, j] + v[k, :, j] * dd
+        return C * (t - T[k] - dd) - np.linalg.norm(r - p)
+
+    glo, ghi = g(lo), g(hi)
+    if not (glo > 0 >= ghi):
+        return None
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if g(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def pin_bracket_bruteforce(orc):
+    """Tiny N: k* equals the unique stored step whose sample is inside the
+    past light cone while the next is not (found by scanning all samples);
+    f_k decreases strictly along the history; the segment root found by
+    sign-change bisection matches the oracle's root."""
+    T, w, v = bunch.wiggly_history(5, 48, 1e-13, beta=0.85, accel_rel=0.15, seed=31)
+    rng = np.random.default_rng(32)
+    x = 1.5e-3 * rng.standard_normal((3, 12))
+    t = T[-1]
+    out = orc.retarded(T, w, v, t, x)
+    ns = len(T)
+    bad = []
+    worst_root = 0.0
+    n_in = n_before = 0
+    for a in range(x.shape[1]):
+        r = x[:, a]
+        for j in range(w.shape[2]):
+            f = C * (t - T) - np.linalg.norm(r[None, :] - w[:, :, j], axis=1)
+            if np.any(np.diff(f) >= 0):
+                bad.append(("nonmonotone", a, j))
+            inside = np.nonzero(f[:-1] > 0)[0]
+            if inside.size:
+                kexp = int(inside.max())
+                back = ns - 1 - kexp
+                root = _segment_root_bisect(r, t, T, w, v, kexp, j, 0.0, T[kexp + 1] - T[kexp])
+                n_in += 1
+            else:
+                back = -1
+                root = _segment_root_bisect(r, t, T, w, v, 0, j, -1e-9, 0.0)
+                n_before += 1
+            if out["kstar"][a, j] != back:
+                bad.append(("kstar", a, j, int(out["kstar"][a, j]), back))
+            if root is None:
+                bad.append(("noroot", a, j))
+            else:
+                worst_root = max(worst_root, abs(out["dt_root"][a, j] - root) / 1e-13)
+    ok = not bad and worst_root < 1e-9 and n_in > 5 and n_before > 5
+    return ok, f"{n_in} in-history, {n_before} before; mismatches {bad[:4]}; root err/dt {worst_root:.2e}"
+
+
+def pin_tie_goes_older(orc):
+    """An exact tie |r - w_k| == c (t - T_k) sends the bracket to the older
+    side: the retarded time lies in [t_0, t_m] when c dt <= |r - w(t_m)|."""
+    ns = 16
+    T, w, v = bunch.uniform_history(ns, 1e-13, np.zeros((3, 1)), np.zeros((3, 1)))
+    t = T[-1]
+    s = ns - 1 - 5  # tie at 5 slots back
+    L = C * (t - T[s])
+    x = np.array([[L], [0.0], [0.0]])
+    ks = orc.retarded(T, w, v, t, x)["kstar"]
+    return int(ks[0, 0]) == 6, f"kstar at an exact tie {int(ks[0, 0])} (expected 6)"
+
+
+def _circle_case(steps_per_period, ns, rho=1e-3, beta=0.6, ntarget=240, seed=41):
+    om = beta * C / rho
+    dt = 2 * math.pi / om / steps_per_period
+    T, w, v = bunch.circular_history(ns, dt, radius=rho, omega=om, exact_velocity=True)
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((3, ntarget))
+    d /= np.linalg.norm(d, axis=0)
+    rad = rng.uniform(2.0, 6.0, ntarget) * C / om
+    x = d * rad
+    return T, w, v, x, rho, om
+
+
+def pin_circle_reconstruction_order(orc):
+    """On an exactly sampled circular orbit the reconstructed t_r, w(t_r),
+    v(t_r) converge at second order in dt and a(t_r) at first order."""
+    errs = []
+    for spp in (400, 800):
+        ns = int(8 * spp)
+        T, w, v, x, rho, om = _circle_case(spp, ns)
+        out = orc.retarded(T, w, v, T[-1], x)
+        tr = circle_retarded_time(x, T[-1], rho, om)
+        we, ve, ae = circle_orbit(tr, rho, om)
+        e_t = np.max(np.abs(out["tr"][:, 0] - tr)) * om
+        e_w = np.max(np.linalg.norm(out["wr"][:, 0, :].T - we, axis=0)) / rho
+        e_v = np.max(np.linalg.norm(out["vr"][:, 0, :].T - ve, axis=0)) / (rho * om)
+        e_a = np.max(np.linalg.norm(out["ar"][:, 0, :].T - ae, axis=0)) / (rho * om * om)
+        errs.append((e_t, e_w, e_v, e_a))
+    r = [errs[0][i] / errs[1][i] for i in range(4)]
+    ok = r[0] > 3.0 and r[1] > 3.0 and r[2] > 3.0 and 1.6 < r[3] < 2.6 and errs[1][3] < 0.02
+    return ok, f"errors at 400/800 steps per turn {errs}; ratios {r}"
+
+
+def pin_circle_field_convergence(orc):
+    """E and B of an exactly sampled circular orbit converge at first order
+    to the exact Lienard-Wiechert field (kappa form, exact retarded time)."""
+    errs = []
+    for spp in (400, 800):
+        ns = int(8 * spp)
+        T, w, v, x, rho, om = _circle_case(spp, ns, seed=42)
+        E, B = orc.fields(T, w, v, QE, T[-1], x)
+        tr = circle_retarded_time(x, T[-1], rho, om)
+        we, ve, ae = circle_orbit(tr, rho, om)
+        Ee, Be = lw_kappa_form(x, we, ve, ae, QE)
+        errs.append((_vec_rel(E, Ee), _vec_rel(B, Be)))
+    rE = errs[0][0] / errs[1][0]
+    rB = errs[0][1] / errs[1][1]
+    ok = 1.6 < rE < 3.2 and 1.6 < rB < 3.2 and errs[1][0] < 0.03 and errs[1][1] < 0.03
+    return ok, f"rel field errors {errs}; ratios E {rE:.2f} B {rB:.2f}"
+
+
+def larmor_flux(orc, steps_per_period=800, rho=1e-3, beta=0.5, Rs_over=3.0, nth=48, nph=96):
+    """Poynting flux of a charge on a circular orbit through a sphere of
+    radius Rs centred on the orbit, and Lienard's power q^2 g^4 a^2 /
+    (6 pi eps0 c^3) for v perpendicular to a."""
+    om = beta * C / rho
+    dt = 2 * math.pi / om / steps_per_period
+    Rs = Rs_over * C / om
+    ns = int((Rs + 2 * rho) / C / dt) + 64
+    T, w, v = bunch.circular_history(ns, dt, radius=rho, omega=om, exact_velocity=True)
+    mu, wmu = np.polynomial.legendre.leggauss(nth)
+    ph = (np.arange(nph) + 0.5) * 2 * math.pi / nph
+    MU, PH = np.meshgrid(mu, ph, indexing="ij")
+    st = np.sqrt(1 - MU**2)
+    n = np.stack([st * np.cos(PH), st * np.sin(PH), MU]).reshape(3, -1)
+    wq = (wmu[:, None] * np.full(nph, 2 * math.pi / nph)[None, :]).reshape(-1)
+    E, B = orc.fields(T, w, v, QE, T[-1], n * Rs)
+    S = np.cross(E.T, B.T).T / MU0
+    flux = float(((S * n).sum(0) * wq).sum() * Rs * Rs)
+    g = 1.0 / math.sqrt(1 - beta * beta)
+    acc = beta * C * om
+    P = QE**2 * g**4 * acc**2 / (6 * math.pi * EPS0 * C**3)
+    return flux, P
+
+
+def pin_larmor(orc):
+    """Flux through a sphere enclosing a circular orbit equals Lienard's
+    radiated power.  The pattern rotates rigidly about the axis, so the
+    field energy inside any centred sphere is constant and the flux through
+    it is the power the charge radiates, at any radius.  The discrete
+    history adds an error of order (omega dt)^2 after the first-order phase
+    errors average out over the sphere: about 1e-4 at 800 steps per turn,
+    bounded here by 1e-3."""
+    f, P = larmor_flux(orc, 800)
+    return abs(f / P - 1) < 1e-3, f"flux/P-1 at 800 steps/turn {f / P - 1:.3e}"
+
+
+def pin_hc_gyration(orc):
+    """Pure magnetic field: |u| is conserved exactly; the per-step rotation
+    tends to the cyclotron angle q B dt / (gamma m) with second-order
+    error; the orbit closes on a circle."""
+    Bz = 0.5
+    u0 = np.array([[2.5 * C], [0.0], [0.3 * C]])
+    g = math.sqrt(1 + (u0**2).sum() / C**2)
+    om = QE * Bz / (g * ME)
+    errs = []
+    worst_mag = 0.0
+    for spp in (64, 128):
+        dt = 2 * math.pi / om / spp
+        u = u0.copy()
+        E = np.zeros((3, 1))
+        B = np.array([[0.0], [0.0], [Bz]])
+        angles = []
+        for _ in range(200):
+            un = orc.hc(-QE, ME, dt, u, E, B)
+            ang = math.atan2(u[0, 0] * un[1, 0] - u[1, 0] * un[0, 0], u[0, 0] * un[0, 0] + u[1, 0] * un[1, 0])
+            angles.append(ang)
+            worst_mag = max(worst_mag, abs(np.linalg.norm(un) / np.linalg.norm(u0) - 1))
+            u = un
+        per = np.array(angles)
+        exact = om * dt  # electrons (q<0) turn counter-clockwise about +z
+        errs.append(abs(per.mean() / exact - 1) + float(np.ptp(per)) / exact)
+    ratio = errs[0] / errs[1]
+    ok = worst_mag < 1e-13 and errs[1] < 1e-3 and 3.2 < ratio < 4.8
+    return ok, f"|u| drift {worst_mag:.2e}; angle rel err {errs}; ratio {ratio:.2f}"
+
+
+def pin_hc_exb_drift(orc):
+    """Crossed E and B: u = gamma_d v_d with v_d = E x B / B^2 is a fixed
+    point of the push (the property that motivates Higuera-Cary)."""
+    E = np.array([[2.0e7], [0.0], [0.0]])
+    B = np.array([[0.0], [0.0], [0.2]])
+    vd = np.cross(E[:, 0], B[:, 0]) / (B[:, 0] @ B[:, 0])
+    gd = 1 / math.sqrt(1 - (vd @ vd) / C**2)
+    u = (gd * vd)[:, None]
+    worst = 0.0
+    uu = u.copy()
+    for _ in range(100):
+        uu = orc.hc(-QE, ME, 1e-11, uu, E, B)
+    worst = float(np.linalg.norm(uu - u) / np.linalg.norm(u))
+    return worst < 1e-13, f"ExB drift fixed-point rel deviation after 100 steps {worst:.2e}"
+
+
+def pin_dipole(orc):
+    """Centred dipole along +z: equatorial field -B0 (RE/r)^3 z-hat, polar
+    field +2 B0 (RE/r)^3 z-hat, zero divergence and curl."""
+    b0, re = 3.12e-5, 6.371e6
+    x = np.array([[re, 0, 0], [0, 3 * re, 0], [0, 0, 2 * re]], dtype=np.float64).T
+    B = orc.dipole(b0, re, x)
+    exp = np.array([[0, 0, -b0], [0, 0, -b0 / 27], [0, 0, 2 * b0 / 8]]).T
+    e1 = float(np.max(np.abs(B - exp)) / b0)
+    rng = np.random.default_rng(5)
+    p = rng.uniform(1.5, 4, (3, 8)) * re * np.sign(rng.standard_normal((3, 8)))
+    h = 1e-4 * re
+    J = np.zeros((3, 3, 8))
+    for c in range(3):
+        dp = np.zeros((3, 1))
+        dp[c] = h
+        J[:, c, :] = (orc.dipole(b0, re, p + dp) - orc.dipole(b0, re, p - dp)) / (2 * h)
+    scale = np.linalg.norm(orc.dipole(b0, re, p), axis=0) / np.linalg.norm(p, axis=0)
+    div = float(np.max(np.abs(J[0, 0] + J[1, 1] + J[2, 2]) / scale))
+    curl = float(np.max(np.abs(np.stack([J[2, 1] - J[1, 2], J[0, 2] - J[2, 0], J[1, 0] - J[0, 1]])) / scale))
+    ok = e1 < 1e-14 and div < 1e-6 and curl < 1e-6
+    return ok, f"axis values rel err {e1:.2e}; div {div:.2e}; curl {curl:.2e}"
+
+
+def pin_step_history(orc):
+    """After stepping (bunch gyrating in a strong dipole field so that the
+    velocity turns by ~1e-2 rad per step): every stored segment moves at
+    its stored velocity (w_{k+1} = w_k + v_k dt), the newest velocity equals
+    u/gamma of the current momenta, the slot times advance by dt, and with
+    no charge and no external field the motion is ballistic."""
+    import oracle as orc_mod
+
+    r, u = bunch.gaussian_bunch(bunch.BunchSpec(12, (1e-3, 1e-3, 1e-3), 1.0, center=(1.0, 0, 0), seed=51))
+    run = orc_mod.OracleRun(orc, r, u, D=16, dt=1e-13, q=-QE, mass=ME, ext_field=1, b0=1.0, re=1.0, nthreads=1)
+    run.step(20)
+    w, v, T = run.w, run.v, run.T
+    seg = np.max(np.abs(w[1:] - (w[:-1] + v[:-1] * 1e-13)))
+    turn = np.max(np.linalg.norm(v[1:] - v[:-1], axis=1)) / C
+    g = np.sqrt(1 + (run.u**2).sum(0) / C**2)
+    newest = np.max(np.abs(v[-1] - run.u / g)) / C
+    tstep = np.max(np.abs(np.diff(T) - 1e-13)) / 1e-13
+    run0 = orc_mod.OracleRun(orc, r, u, D=16, dt=1e-13, q=0.0, mass=ME, nthreads=1)
+    run0.step(30)
+    g0 = np.sqrt(1 + (u**2).sum(0) / C**2)
+    ball = np.max(np.abs(run0.y - (r + u / g0 * 30e-13)))
+    ok = seg < 1e-14 and turn > 1e-5 and newest < 1e-15 and tstep < 1e-6 and ball < 1e-14 and run.n[0] == 20
+    return ok, (f"segment {seg:.2e} m (velocity turn/step {turn:.1e} c), newest v {newest:.2e} c, "
+                f"dT {tstep:.2e}, ballistic {ball:.2e} m")
+
+
+def pin_diag(orc):
+    """RMS sizes, centroid and mean kinetic energy against numpy."""
+    r, u = bunch.gaussian_bunch(bunch.BunchSpec(500, (1e-3, 2e-3, 3e-3), 1.0, center=(5.0, 0, 0), seed=61))
+    d = orc.diag(r, u, ME)
+    g = np.sqrt(1 + (u**2).sum(0) / C**2)
+    ek = ((g - 1) * ME * C * C).mean()
+    exp = [r[0].std(), r[1].std(), r[2].std(), 0.5 * (r[0].std() + r[1].std()), r[0].mean(), r[1].mean(),
+           r[2].mean(), ek]
+    err = max(abs(a - b) / abs(b) for a, b in zip(d, exp))
+    return err < 1e-10, f"diag rel err {err:.2e}"
+
+
+ALL_PINS = [
+    pin_constants, pin_uniform_retarded_time, pin_heaviside_feynman, pin_coulomb, pin_before_history_field,
+    pin_bracket_bruteforce, pin_tie_goes_older, pin_circle_reconstruction_order, pin_circle_field_convergence,
+    pin_larmor, pin_hc_gyration, pin_hc_exb_drift, pin_dipole, pin_step_history, pin_diag,
+]

@@ -1,0 +1,69 @@
+"""Printed values of the paper and the seeded input generators."""
+import json
+import math
+import os
+
+import numpy as np
+
+from paper_2605_05543_amd import bunch
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+C = 299792458.0
+
+
+def test_beam_table_gamma_beta():
+    """Sec. 2.5 table: 1 MeV electrons have gamma0 = 2.96 and beta = 0.941."""
+    t = GOLD["beam_table"]
+    g = float(bunch.gamma_of_kinetic(t["E0_MeV"] * bunch.MEV))
+    beta = math.sqrt(1 - 1 / g**2)
+    assert round(g, 2) == t["gamma0"]
+    assert round(beta, 3) == t["beta"]
+
+
+def test_snapshot_centroid_is_ballistic():
+    """The printed snapshot times and centroids move at ~beta c (the bunch
+    coasts along z while it expands): zbar / t within 1% of 0.941 c."""
+    beta = GOLD["beam_table"]["beta"]
+    for case in GOLD["snapshots"]["cases"]:
+        assert abs(case["zbar_m"] / case["t_s"] / (beta * C) - 1) < 0.01
+
+
+def test_dipole_moment_vs_surface_field():
+    """The paper's M0 = 8.6e22 A m^2 gives an equatorial surface field of
+    (mu0/4pi) M0 / RE^3 ~ 3.33e-5 T; the workloads use 3.12e-5 T (M0 is then
+    8.07e22 A m^2)."""
+    mu0 = 1.25663706212e-6
+    b_eq = mu0 / (4 * math.pi) * GOLD["dipole"]["M0_A_m2"] / bunch.R_EARTH**3
+    assert abs(b_eq - 3.33e-5) < 0.01e-5
+
+
+def test_gaussian_bunch_moments():
+    spec = bunch.BunchSpec(20000, (1e-3, 2e-3, 3e-3), 1.0, center=(1.0, 2.0, 3.0), seed=9)
+    r, u = bunch.gaussian_bunch(spec)
+    assert np.allclose(r.mean(1), [1.0, 2.0, 3.0], atol=1e-4)
+    assert np.allclose(r.std(1), [1e-3, 2e-3, 3e-3], rtol=0.03)
+    g = np.sqrt(1 + (u**2).sum(0) / C**2)
+    kin = (g - 1) * bunch.M_ELECTRON * C**2 / bunch.MEV
+    assert abs(kin.mean() - 1.0) < 1e-4 and abs(kin.std() - 1e-3) < 1e-4
+    ang = np.arctan2(np.hypot(u[0], u[1]), u[2])
+    assert abs(np.sqrt((ang**2).mean()) - math.sqrt(2) * 1e-3) < 5e-5
+    r2, u2 = bunch.gaussian_bunch(spec)
+    assert np.array_equal(r, r2) and np.array_equal(u, u2)
+
+
+def test_paper_beam_sampling():
+    """Sec. 2.5 sampling: mean v_z shifted back to v0; transverse velocity
+    spread eps_r v0 / r_perp."""
+    r, u = bunch.paper_beam(4000, seed=3)
+    g = np.sqrt(1 + (u**2).sum(0) / C**2)
+    vel = u / g
+    g0 = float(bunch.gamma_of_kinetic(bunch.MEV))
+    v0 = C * math.sqrt(1 - 1 / g0**2)
+    assert abs(vel[2].mean() / v0 - 1) < 1e-12
+    assert abs(vel[0].std() / (1e-6 * v0 / 2e-3) - 1) < 0.05
+
+
+def test_histories_move_at_stored_velocity():
+    T, w, v = bunch.wiggly_history(3, 20, 1e-13, seed=1)
+    assert np.max(np.abs(w[1:] - (w[:-1] + v[:-1] * np.diff(T)[:, None, None]))) < 1e-18
+    assert np.all(np.linalg.norm(v, axis=1) < C)

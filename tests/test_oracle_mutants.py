@@ -1,0 +1,39 @@
+"""Plant one plausible mistake at a time in the oracle (compile-time
+MUT_* switches in oracle/empp_oracle.c) and check that the pins catch it.
+This shows that the pins constrain every step of the oracle: the
+bracket rule, the root, the reconstruction, the LW formula, B, the pusher,
+the dipole and the history update."""
+import pytest
+
+import oracle
+import pins
+
+MUTANTS = [
+    "MUT_TIE_NEWER",          # ties sent to the newer half
+    "MUT_KSTAR_OLDER",        # bracket one slot too old
+    "MUT_ROOT_PLUS",          # the discarded '+' root of Eq. (dt)
+    "MUT_ACCEL_BEFORE_RING",  # non-zero acceleration out of history
+    "MUT_NO_VINTERP",         # v(t_r) = v_1 (no interpolation)
+    "MUT_VPRIME_NOHAT",       # v' = c eta - v instead of c eta_hat - v
+    "MUT_DROP_ACCEL",         # radiation term dropped
+    "MUT_B_SIGN",             # B = E x eta_hat / c
+    "MUT_DIPOLE_SIGN",        # wrong sign of the 3 (M.r) r term
+    "MUT_HC_TYPO",            # u- x t in the last HC step
+    "MUT_NO_FINALISE",        # newest history velocity never finalised
+]
+
+
+@pytest.mark.parametrize("mutant", MUTANTS)
+def test_mutant_is_caught(mutant, tmp_path):
+    lib = oracle.build_mutant(mutant, str(tmp_path))
+    orc = oracle.Oracle(lib)
+    failed = []
+    for pin in pins.ALL_PINS:
+        try:
+            ok, _ = pin(orc)
+        except Exception:  # an exception is a failed pin as well
+            ok = False
+        if not ok:
+            failed.append(pin.__name__)
+    print(mutant, "caught by", failed)
+    assert failed, f"{mutant} passes every pin"
