@@ -72,6 +72,8 @@ class Oracle:
         L.oracle_constants.argtypes = [_P]
         L.oracle_retarded.argtypes = [_I64, _I32, _P, _P, _P, _D, _I64, _P, _P, _P, _P, _P, _P, _P, _P]
         L.oracle_fields.argtypes = [_I64, _I32, _P, _P, _P, _D, _D, _I64, _P, _P, _P, _P, _P, ctypes.c_int, _P]
+        L.oracle_fields_abs.argtypes = [_I64, _I32, _P, _P, _P, _D, _D, _I64, _P, _P, _P, _P, _P, _P, _P,
+                                        ctypes.c_int, _P]
         L.oracle_dipole.argtypes = [_D, _D, _I64, _P, _P]
         L.oracle_dipole.restype = None
         L.oracle_hc.argtypes = [_D, _D, _D, _I64, _P, _P, _P]
@@ -109,7 +111,7 @@ class Oracle:
         return dict(kstar=kstar, dt_root=dt_root, tr=tr, wr=wr, vr=vr, ar=ar)
 
     # -- Sec. 2.1 fields ---------------------------------------------------------
-    def fields(self, T, w, v, q, t, x, self_index=None, want_kstar=False, nthreads=None):
+    def fields(self, T, w, v, q, t, x, self_index=None, want_kstar=False, nthreads=None, want_abs=False):
         T, w, v, x = _f64(T), _f64(w), _f64(v), _f64(x)
         ns, _, N = w.shape
         m = x.shape[1]
@@ -117,13 +119,20 @@ class Oracle:
         E = np.zeros((3, m))
         B = np.zeros((3, m))
         kstar = np.zeros((m, N), np.int32) if want_kstar else None
+        SE = np.zeros(m) if want_abs else None
+        SB = np.zeros(m) if want_abs else None
         bad = np.full(2, -1, np.int64)
         nt = nthreads or self.max_threads()
-        st = self.L.oracle_fields(N, ns, _ptr(T), _ptr(w), _ptr(v), float(q), float(t), m, _ptr(x), _ptr(si),
-                                  _ptr(E), _ptr(B), _ptr(kstar), int(nt), _ptr(bad))
+        st = self.L.oracle_fields_abs(N, ns, _ptr(T), _ptr(w), _ptr(v), float(q), float(t), m, _ptr(x), _ptr(si),
+                                      _ptr(E), _ptr(B), _ptr(kstar), _ptr(SE), _ptr(SB), int(nt), _ptr(bad))
         if st != OR_OK:
             raise OracleError(st, tuple(bad))
-        return (E, B, kstar) if want_kstar else (E, B)
+        out = (E, B)
+        if want_kstar:
+            out = out + (kstar,)
+        if want_abs:
+            out = out + (SE, SB)
+        return out
 
     def dipole(self, b0, re, x):
         x = _f64(x)

@@ -121,6 +121,7 @@ typedef struct {
     double wr[3];     /* w(t_r) (Eq. linear / linear2)                      */
     double vr[3];     /* v(t_r)                                             */
     double ar[3];     /* a(t_r)                                             */
+    double eta[3];    /* r - w(t_r), formed as (r - w_1) - v_1 dt           */
 } retarded_t;
 
 /* Sec. 2.2 retarded-time determination for target position r at time t
@@ -203,8 +204,19 @@ static int solve_retarded(int64_t N, int32_t ns, const double *T, const double *
     out->before = before;
     out->dt_root = dtr;
     out->tr = T[s1] + dtr;
-    for (int c = 0; c < 3; ++c)
+    /* eta = r - w(t_r) with w(t_r) = w_1 + v_1 dt.  It is formed as
+     * (r - w_1) - v_1 dt: r - w_1 is exact for nearby points, whereas the
+     * absolute w(t_r) would be rounded to the spacing of doubles at its
+     * coordinates (3.7 nm at three Earth radii), a relative error of ~1e-6
+     * of a millimetre separation.                                         */
+    for (int c = 0; c < 3; ++c) {
         out->wr[c] = w1[c] + v1[c] * dtr;
+#ifdef MUT_ETA_ABSOLUTE
+        out->eta[c] = r[c] - out->wr[c];
+#else
+        out->eta[c] = d[c] - v1[c] * dtr;
+#endif
+    }
     if (before) {
         for (int c = 0; c < 3; ++c) {
             out->vr[c] = v1[c];
@@ -240,7 +252,8 @@ static int solve_retarded(int64_t N, int32_t ns, const double *T, const double *
  *   B = eta_hat x E / c.                                                    */
 static int lw_field(const double r[3], const retarded_t *rt, double q, double E[3], double B[3])
 {
-    double eta[3] = {r[0] - rt->wr[0], r[1] - rt->wr[1], r[2] - rt->wr[2]};
+    const double *eta = rt->eta;
+    (void)r;
     double en = sqrt(dot3(eta, eta));
     if (!(en > 0.0))
         return OR_ENUMERIC;
@@ -312,6 +325,11 @@ int oracle_retarded(int64_t N, int32_t ns, const double *T, const double *w, con
     return OR_OK;
 }
 
+int oracle_fields_abs(int64_t N, int32_t ns, const double *T, const double *w, const double *v,
+                      double q, double t, int64_t m, const double *x, const int64_t *self_index,
+                      double *E, double *B, int32_t *kstar, double *SE, double *SB, int nthreads,
+                      int64_t *bad);
+
 /* Sec. 2.1 superposition: E_i = sum_{j != i} E_ij and the same for B,
  * each sum Neumaier-compensated over j in index order.  q is the charge
  * of every source (all macro-particles carry the same charge and weight).
@@ -320,6 +338,18 @@ int oracle_retarded(int64_t N, int32_t ns, const double *T, const double *w, con
 int oracle_fields(int64_t N, int32_t ns, const double *T, const double *w, const double *v,
                   double q, double t, int64_t m, const double *x, const int64_t *self_index,
                   double *E, double *B, int32_t *kstar, int nthreads, int64_t *bad)
+{
+    return oracle_fields_abs(N, ns, T, w, v, q, t, m, x, self_index, E, B, kstar, NULL, NULL,
+                             nthreads, bad);
+}
+
+/* As oracle_fields, and also S_E[a] = sum_j |E_aj|, S_B[a] = sum_j |B_aj|
+ * (either may be NULL): the scale against which a sum's rounding error
+ * is judged.                                                            */
+int oracle_fields_abs(int64_t N, int32_t ns, const double *T, const double *w, const double *v,
+                      double q, double t, int64_t m, const double *x, const int64_t *self_index,
+                      double *E, double *B, int32_t *kstar, double *SE, double *SB, int nthreads,
+                      int64_t *bad)
 {
     if (N < 1 || ns < 2 || m < 0 || !T || !w || !v || !x || !E || !B)
         return OR_EINVAL;
@@ -334,12 +364,22 @@ int oracle_fields(int64_t N, int32_t ns, const double *T, const double *w, const
         double r[3] = {x[a], x[m + a], x[2 * m + a]};
         double sE[3] = {0, 0, 0}, cE[3] = {0, 0, 0};
         double sB[3] = {0, 0, 0}, cB[3] = {0, 0, 0};
+        double aE = 0.0, aB = 0.0;
         int st = OR_OK;
         int64_t jfail = -1;
         for (int64_t j = 0; j < N; ++j) {
             if (self_index && self_index[a] == j) {
                 if (kstar) kstar[a * N + j] = 0;
                 continue;
+            }
+            /* A target on a source's present position has eta = 0 at
+             * t_r = t: the field is undefined (Sec. 2.1 divides by eta). */
+            double wn[3];
+            load_sample(w, N, ns - 1, j, wn);
+            if (r[0] == wn[0] && r[1] == wn[1] && r[2] == wn[2]) {
+                st = OR_ENUMERIC;
+                jfail = j;
+                break;
             }
             retarded_t rt;
             st = solve_retarded(N, ns, T, w, v, j, r, t, &rt);
@@ -356,7 +396,11 @@ int oracle_fields(int64_t N, int32_t ns, const double *T, const double *w, const
                 neumaier_add(&sE[c], &cE[c], Eij[c]);
                 neumaier_add(&sB[c], &cB[c], Bij[c]);
             }
+            aE += sqrt(dot3(Eij, Eij));
+            aB += sqrt(dot3(Bij, Bij));
         }
+        if (SE) SE[a] = aE;
+        if (SB) SB[a] = aB;
         for (int c = 0; c < 3; ++c) {
             E[c * m + a] = sE[c] + cE[c];
             B[c * m + a] = sB[c] + cB[c];

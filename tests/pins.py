@@ -162,6 +162,36 @@ def pin_heaviside_feynman(orc):
     return ok, f"HF max rel err E {worst_e:.3e} B {worst_b:.3e}"
 
 
+def pin_heaviside_feynman_far(orc):
+    """Heaviside-Feynman with the sources and targets three Earth radii from
+    the origin: millimetre separations on top of 1.9e7 m coordinates must
+    not lose accuracy (eta is a small difference of two large absolute
+    positions).  All inputs are exact multiples of the spacing of doubles
+    there (2^-28 m), and dt = 2^-43 s, so the stored history is exactly
+    straight and any error comes from the field evaluation itself."""
+    q = 2.0**-28
+    dt = 2.0**-43
+    ns = 64
+    rng = np.random.default_rng(14)
+    off = np.array([3 * 6.371e6, 0.0, 0.0])
+    worst = 0.0
+    for j in range(4):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        step = np.round(0.9 * C * dt * d / q) * q          # exact multiple of q
+        vel = step / dt                                      # exact (power-of-two scale)
+        w_now = off + np.round(1e-3 * rng.standard_normal(3) / q) * q
+        k = np.arange(-(ns - 1), 1, dtype=np.float64)
+        T = k * dt
+        w = (w_now[None, :] + k[:, None] * step[None, :])[:, :, None]
+        v = np.broadcast_to(vel[None, :, None], w.shape).copy()
+        x = off[:, None] + np.round(2e-3 * rng.standard_normal((3, 30)) / q) * q
+        E, _ = orc.fields(T, w, v, -QE, T[-1], x)
+        Eh, _ = heaviside_feynman(x - w_now[:, None], vel[:, None], -QE)
+        worst = max(worst, _vec_rel(E, Eh))
+    return worst < 1e-12, f"HF at 3 R_E max rel err E {worst:.3e}"
+
+
 def pin_coulomb(orc):
     """A source at rest gives k q Rhat / R^2 and no magnetic field."""
     rng = np.random.default_rng(13)
@@ -465,7 +495,7 @@ def pin_diag(orc):
 
 
 ALL_PINS = [
-    pin_constants, pin_uniform_retarded_time, pin_heaviside_feynman, pin_coulomb, pin_before_history_field,
+    pin_constants, pin_uniform_retarded_time, pin_heaviside_feynman, pin_heaviside_feynman_far, pin_coulomb, pin_before_history_field,
     pin_bracket_bruteforce, pin_tie_goes_older, pin_circle_reconstruction_order, pin_circle_field_convergence,
     pin_larmor, pin_hc_gyration, pin_hc_exb_drift, pin_dipole, pin_step_history, pin_diag,
 ]

@@ -20,6 +20,7 @@ MUTANTS = [
     "MUT_DIPOLE_SIGN",        # wrong sign of the 3 (M.r) r term
     "MUT_HC_TYPO",            # u- x t in the last HC step
     "MUT_NO_FINALISE",        # newest history velocity never finalised
+    "MUT_ETA_ABSOLUTE",       # eta from the rounded absolute retarded position
 ]
 
 
