@@ -1,0 +1,193 @@
+/*
+ * empp.h -- C ABI of libempp.so, the MI355X (gfx950) implementation of the
+ * hot path of the electromagnetic particle-particle (EM-PP) method for
+ * relativistic electron bunches (arXiv 2605.05543).
+ *
+ * What one step computes (fixed time step dt, present time T_n):
+ *   1. For every target particle i and every other source j, the retarded
+ *      time on j's stored trajectory history: bracket by the light-cone
+ *      sign test, then the segment quadratic and linear reconstruction
+ *      (Sec. 2.2, Eqs. dt, linear, linear2).
+ *   2. The Lienard-Wiechert velocity and acceleration fields of that pair
+ *      (Sec. 2.1, Eqs. LW_E, LW_B), summed over j != i with compensated
+ *      accumulation (superposition, Sec. 2.1).
+ *   3. A Higuera-Cary push of every particle in its self-field plus the
+ *      centred-dipole geomagnetic field (Secs. 2.3 and 2.6), the drift, and
+ *      the history update.
+ *
+ * Units are SI throughout.  Host arrays are component-major: a [3][N]
+ * array holds x[0..N), then y[0..N), then z[0..N).  A history is given
+ * oldest slot first: T[ns], w[ns][3][N] (positions), v[ns][3][N]
+ * (velocities).  Slot k's velocity is the one that carries the particle
+ * from T_k to T_{k+1}; the newest slot's velocity is provisional until the
+ * next push finalises it.
+ *
+ * Ownership: every pointer argument is borrowed for the duration of the
+ * call.  Host inputs are copied; host outputs are written before return.
+ * Device pointers (the *_dev entry points and the optional workspace) stay
+ * owned by the caller; the library never frees them.  Memory the library
+ * allocates itself is released by empp_destroy.
+ *
+ * Streams: all device work of a context is issued on the stream given in
+ * its configuration (NULL: the device's null stream).  empp_step and the
+ * *_dev calls only enqueue work; calls that return host data synchronise
+ * the stream first.  Errors detected by kernels (coincident particles, a
+ * negative discriminant) are latched on the device and reported by the
+ * next synchronising call (empp_sync, the getters, empp_fields_at).
+ *
+ * Threading: a context is bound to one device and must not be used by two
+ * threads at once.  Different contexts are independent.
+ *
+ * Errors: every call returns an empp_status and never aborts or throws.
+ * empp_last_error() returns a thread-local description of the last
+ * failure on the calling thread.
+ */
+#ifndef EMPP_H
+#define EMPP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct empp_ctx empp_ctx;
+
+typedef enum {
+    EMPP_OK = 0,
+    EMPP_EINVAL = 1,       /* invalid argument or configuration            */
+    EMPP_ENOMEM = 2,       /* device or host allocation failed             */
+    EMPP_EDEVICE = 3,      /* HIP runtime error (message has its text)     */
+    EMPP_ESTATE = 4,       /* call not valid in the context's state        */
+    EMPP_ENUMERIC = 5,     /* coincident particles or negative discriminant */
+    EMPP_EUNSUPPORTED = 6  /* option not available in this build           */
+} empp_status;
+
+typedef enum {
+    EMPP_FP64 = 0,  /* everything in double precision                      */
+    EMPP_MIXED = 1  /* FP64 absolute positions/times, FP32 offsets and LW
+                       terms with two-sum accumulation, FP64 re-test of
+                       light-cone signs inside the FP32 rounding band      */
+} empp_precision;
+
+typedef enum {
+    EMPP_GUESS_BISECT = 0,    /* the paper's search: oldest-sample test, then
+                                 bisection of the whole history            */
+    EMPP_GUESS_MLP = 1,       /* start from the surrogate network's delay  */
+    EMPP_GUESS_BALLISTIC = 2  /* start from the closed-form delay of a source
+                                 coasting with its newest velocity          */
+} empp_guess;
+
+typedef struct {
+    int64_t n;             /* particles, >= 2                                */
+    int32_t depth;         /* history slots D, 2 <= D <= 65536               */
+    int32_t ext_field;     /* 0: none; 1: centred dipole, moment along +z    */
+    double q;              /* charge of every macro-particle (C)             */
+    double m;              /* mass of every macro-particle (kg), > 0         */
+    double dt;             /* fixed time step (s), > 0                       */
+    double dipole_b0;      /* dipole equatorial field at radius dipole_re (T) */
+    double dipole_re;      /* reference radius of dipole_b0 (m)              */
+    int32_t precision;     /* empp_precision                                 */
+    int32_t guess;         /* empp_guess                                     */
+    int32_t device;        /* HIP device ordinal                             */
+    int32_t source_splits; /* 0: automatic; else number of source chunks     */
+    void *stream;          /* hipStream_t or NULL                            */
+    void *workspace;       /* caller-owned device memory, or NULL            */
+    uint64_t workspace_bytes;
+} empp_config;
+
+typedef struct {
+    double sigma[3];       /* RMS sizes sigma_x, sigma_y, sigma_z (Sec. 2.5)  */
+    double sigma_xy;       /* (sigma_x + sigma_y)/2                          */
+    double centroid[3];    /* mean position (weights 1)                      */
+    double mean_kinetic;   /* mean kinetic energy (gamma-1) m c^2, J (Sec. 2.7) */
+    double t;              /* present time                                   */
+    int64_t step;          /* steps taken since the history was set          */
+} empp_diag;
+
+typedef struct {
+    uint64_t pairs;        /* (target, source) pairs evaluated               */
+    uint64_t before;       /* pairs whose retarded time precedes the history */
+    uint64_t probes;       /* light-cone sign tests performed                */
+    uint64_t rescues;      /* FP64 re-tests of FP32 signs (mixed precision)  */
+    uint64_t fallbacks;    /* guided searches that fell back to bisection    */
+} empp_counters;
+
+/* Device memory a context needs for cfg (bytes), so that a caller can
+ * supply it through cfg->workspace.  EINVAL on a bad configuration.     */
+empp_status empp_workspace_size(const empp_config *cfg, uint64_t *bytes);
+
+/* Create a context on cfg->device.  With cfg->workspace NULL the library
+ * allocates its device memory itself; otherwise the caller's buffer must
+ * hold at least empp_workspace_size bytes, 256-byte aligned.            */
+empp_status empp_create(const empp_config *cfg, empp_ctx **out);
+
+/* Release the context and everything the library allocated.  NULL-safe. */
+void empp_destroy(empp_ctx *ctx);
+
+const char *empp_last_error(void);
+
+/* Set the bunch: positions r[3][N] and proper velocities u[3][N]
+ * (u = gamma v, m/s) at time t0 (host arrays).  The history is built by
+ * empp_init_history_straight.  EINVAL on non-finite values.             */
+empp_status empp_init_bunch(empp_ctx *ctx, const double *r, const double *u, double t0);
+
+/* Straight-line prior history: slots k = -(D-1)..0 at T_k = t0 + k dt with
+ * w_k = r + v0 (k dt), v_k = v0 = u / gamma (the particle coasted with its
+ * initial velocity).  The present time becomes t0, step index 0.        */
+empp_status empp_init_history_straight(empp_ctx *ctx);
+
+/* Install an explicit history (host arrays, nslots == D, oldest first,
+ * T strictly increasing) and the present proper velocities u[3][N].  The
+ * present time is T[nslots-1]; later steps advance it by dt.  EINVAL when
+ * a stored speed is >= c or a value is not finite.                       */
+empp_status empp_set_history(empp_ctx *ctx, int32_t nslots, const double *T, const double *w,
+                             const double *v, const double *u);
+
+/* Advance nsteps fixed steps (asynchronous).                             */
+empp_status empp_step(empp_ctx *ctx, int64_t nsteps);
+
+/* Fields at m external points x[3][m] (host) at the present time t (t must
+ * equal it exactly: EINVAL otherwise).  self_index[m] (or NULL) names a
+ * source to leave out per target (-1: none).  Outputs E[3][m], B[3][m]
+ * (self-fields only, no external field) and, if kstar is not NULL,
+ * kstar[m][N]: for each pair the number of slots back from the newest of
+ * the bracket's older end (1..D-1), -1 when the retarded time precedes the
+ * history, 0 for a skipped pair.  Synchronous.                           */
+empp_status empp_fields_at(empp_ctx *ctx, double t, int64_t m, const double *x,
+                           const int64_t *self_index, double *E, double *B, int32_t *kstar);
+
+/* Same with device pointers (same layouts); asynchronous on the context's
+ * stream.  kstar_dev may be NULL.                                       */
+empp_status empp_fields_at_dev(empp_ctx *ctx, double t, int64_t m, const double *x_dev,
+                               const int64_t *self_index_dev, double *E_dev, double *B_dev,
+                               int32_t *kstar_dev);
+
+/* Present positions r[3][N], proper velocities u[3][N], time and step
+ * index (host; any output may be NULL).                                  */
+empp_status empp_get_state(empp_ctx *ctx, double *r, double *u, double *t, int64_t *step);
+
+/* Whole history, oldest first: T[D], w[D][3][N], v[D][3][N] (host).      */
+empp_status empp_get_history(empp_ctx *ctx, double *T, double *w, double *v);
+
+/* Self-fields E[3][N], B[3][N] that the last step's push used (host).    */
+empp_status empp_get_fields(empp_ctx *ctx, double *E, double *B);
+
+empp_status empp_get_diag(empp_ctx *ctx, empp_diag *out);
+
+/* Counters accumulated since the last reset (the counting kernels run
+ * only while counting is enabled).                                       */
+empp_status empp_set_counting(empp_ctx *ctx, int32_t enable);
+empp_status empp_get_counters(empp_ctx *ctx, empp_counters *out);
+
+/* Wait for the context's stream and report latched device errors.        */
+empp_status empp_sync(empp_ctx *ctx);
+
+/* Change precision / search mode of an existing context.                 */
+empp_status empp_set_mode(empp_ctx *ctx, int32_t precision, int32_t guess);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMPP_H */

@@ -1,0 +1,298 @@
+"""ctypes binding of libempp.so (the C ABI in include/empp.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  The functions keep the C names; ``Context`` is a small
+convenience wrapper that owns one ``empp_ctx``.  If the library is
+missing the import of this module fails loudly -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libempp.so")
+
+EMPP_OK, EMPP_EINVAL, EMPP_ENOMEM, EMPP_EDEVICE, EMPP_ESTATE, EMPP_ENUMERIC, EMPP_EUNSUPPORTED = range(7)
+STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ESTATE", "ENUMERIC", "EUNSUPPORTED"]
+EMPP_FP64, EMPP_MIXED = 0, 1
+EMPP_GUESS_BISECT, EMPP_GUESS_MLP, EMPP_GUESS_BALLISTIC = 0, 1, 2
+
+# Functions declared in include/empp.h (tests check that each is exported).
+EXPORTS = [
+    "empp_workspace_size", "empp_create", "empp_destroy", "empp_last_error", "empp_init_bunch",
+    "empp_init_history_straight", "empp_set_history", "empp_step", "empp_fields_at", "empp_fields_at_dev",
+    "empp_get_state", "empp_get_history", "empp_get_fields", "empp_get_diag", "empp_set_counting",
+    "empp_get_counters", "empp_sync", "empp_set_mode",
+]
+
+
+class EmppError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"EMPP_{name}: {message}")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("depth", ctypes.c_int32), ("ext_field", ctypes.c_int32),
+        ("q", ctypes.c_double), ("m", ctypes.c_double), ("dt", ctypes.c_double),
+        ("dipole_b0", ctypes.c_double), ("dipole_re", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("guess", ctypes.c_int32), ("device", ctypes.c_int32),
+        ("source_splits", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_uint64),
+    ]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double * 3), ("sigma_xy", ctypes.c_double), ("centroid", ctypes.c_double * 3),
+                ("mean_kinetic", ctypes.c_double), ("t", ctypes.c_double), ("step", ctypes.c_int64)]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_uint64), ("before", ctypes.c_uint64), ("probes", ctypes.c_uint64),
+                ("rescues", ctypes.c_uint64), ("fallbacks", ctypes.c_uint64)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "empp_workspace_size": [ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_uint64)],
+        "empp_create": [ctypes.POINTER(Config), ctypes.POINTER(_P)],
+        "empp_init_bunch": [_P, _P, _P, _D],
+        "empp_init_history_straight": [_P],
+        "empp_set_history": [_P, _I32, _P, _P, _P, _P],
+        "empp_step": [_P, _I64],
+        "empp_fields_at": [_P, _D, _I64, _P, _P, _P, _P, _P],
+        "empp_fields_at_dev": [_P, _D, _I64, _P, _P, _P, _P, _P],
+        "empp_get_state": [_P, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_I64)],
+        "empp_get_history": [_P, _P, _P, _P],
+        "empp_get_fields": [_P, _P, _P],
+        "empp_get_diag": [_P, ctypes.POINTER(Diag)],
+        "empp_set_counting": [_P, _I32],
+        "empp_get_counters": [_P, ctypes.POINTER(Counters)],
+        "empp_sync": [_P],
+        "empp_set_mode": [_P, _I32, _I32],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.empp_destroy.argtypes = [_P]
+    L.empp_destroy.restype = None
+    L.empp_last_error.argtypes = []
+    L.empp_last_error.restype = ctypes.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != EMPP_OK:
+        raise EmppError(status, lib.empp_last_error().decode(errors="replace"))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# -- thin wrappers with the C names -------------------------------------------------
+
+def empp_workspace_size(cfg: Config) -> int:
+    out = ctypes.c_uint64()
+    _check(lib.empp_workspace_size(ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def empp_create(cfg: Config):
+    h = _P()
+    _check(lib.empp_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h
+
+
+def empp_destroy(h):
+    lib.empp_destroy(h)
+
+
+def empp_init_bunch(h, r, u, t0=0.0):
+    _check(lib.empp_init_bunch(h, _ptr(_f64(r)), _ptr(_f64(u)), float(t0)))
+
+
+def empp_init_history_straight(h):
+    _check(lib.empp_init_history_straight(h))
+
+
+def empp_set_history(h, T, w, v, u):
+    T, w, v, u = _f64(T), _f64(w), _f64(v), _f64(u)
+    _check(lib.empp_set_history(h, int(T.shape[0]), _ptr(T), _ptr(w), _ptr(v), _ptr(u)))
+
+
+def empp_step(h, nsteps=1):
+    _check(lib.empp_step(h, int(nsteps)))
+
+
+def empp_fields_at(h, t, x, n_src, self_index=None, want_kstar=False):
+    x = _f64(x)
+    m = x.shape[1]
+    si = None if self_index is None else np.ascontiguousarray(self_index, dtype=np.int64)
+    E = np.zeros((3, m))
+    B = np.zeros((3, m))
+    ks = np.zeros((m, n_src), np.int32) if want_kstar else None
+    _check(lib.empp_fields_at(h, float(t), m, _ptr(x), _ptr(si), _ptr(E), _ptr(B), _ptr(ks)))
+    return (E, B, ks) if want_kstar else (E, B)
+
+
+def empp_fields_at_dev(h, t, m, x_ptr, self_ptr, E_ptr, B_ptr, kstar_ptr=None):
+    _check(lib.empp_fields_at_dev(h, float(t), int(m), x_ptr, self_ptr, E_ptr, B_ptr, kstar_ptr))
+
+
+def empp_get_state(h, n):
+    r = np.zeros((3, n))
+    u = np.zeros((3, n))
+    t = _D()
+    s = _I64()
+    _check(lib.empp_get_state(h, _ptr(r), _ptr(u), ctypes.byref(t), ctypes.byref(s)))
+    return r, u, t.value, s.value
+
+
+def empp_get_history(h, n, depth):
+    T = np.zeros(depth)
+    w = np.zeros((depth, 3, n))
+    v = np.zeros((depth, 3, n))
+    _check(lib.empp_get_history(h, _ptr(T), _ptr(w), _ptr(v)))
+    return T, w, v
+
+
+def empp_get_fields(h, n):
+    E = np.zeros((3, n))
+    B = np.zeros((3, n))
+    _check(lib.empp_get_fields(h, _ptr(E), _ptr(B)))
+    return E, B
+
+
+def empp_get_diag(h):
+    d = Diag()
+    _check(lib.empp_get_diag(h, ctypes.byref(d)))
+    return {"sigma": list(d.sigma), "sigma_xy": d.sigma_xy, "centroid": list(d.centroid),
+            "mean_kinetic": d.mean_kinetic, "t": d.t, "step": d.step}
+
+
+def empp_set_counting(h, enable=True):
+    _check(lib.empp_set_counting(h, 1 if enable else 0))
+
+
+def empp_get_counters(h):
+    c = Counters()
+    _check(lib.empp_get_counters(h, ctypes.byref(c)))
+    return {"pairs": c.pairs, "before": c.before, "probes": c.probes, "rescues": c.rescues,
+            "fallbacks": c.fallbacks}
+
+
+def empp_sync(h):
+    _check(lib.empp_sync(h))
+
+
+def empp_set_mode(h, precision, guess):
+    _check(lib.empp_set_mode(h, int(precision), int(guess)))
+
+
+class Context:
+    """One empp_ctx.  Device memory comes from a torch tensor (PyTorch is
+    the allocator and stream provider); kernels run on torch's current
+    stream of ``device``."""
+
+    def __init__(self, *, n, depth, q, m, dt, ext_field=0, dipole_b0=0.0, dipole_re=0.0,
+                 precision=EMPP_FP64, guess=EMPP_GUESS_BISECT, device=0, source_splits=0, use_torch=True):
+        self.n, self.depth = int(n), int(depth)
+        cfg = Config(n=self.n, depth=self.depth, ext_field=int(ext_field), q=float(q), m=float(m), dt=float(dt),
+                     dipole_b0=float(dipole_b0), dipole_re=float(dipole_re), precision=int(precision),
+                     guess=int(guess), device=int(device), source_splits=int(source_splits))
+        self._ws = None
+        self.stream_handle = None
+        if use_torch:
+            import torch
+
+            dev = torch.device("cuda", device)
+            nbytes = empp_workspace_size(cfg)
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            base = self._ws.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            cfg.workspace = aligned
+            cfg.workspace_bytes = nbytes
+            self.stream_handle = torch.cuda.current_stream(dev).cuda_stream
+            cfg.stream = self.stream_handle
+        self.cfg = cfg
+        self.h = empp_create(cfg)
+
+    def close(self):
+        if self.h:
+            empp_destroy(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def init_bunch(self, r, u, t0=0.0):
+        empp_init_bunch(self.h, r, u, t0)
+
+    def init_history_straight(self):
+        empp_init_history_straight(self.h)
+
+    def set_history(self, T, w, v, u):
+        empp_set_history(self.h, T, w, v, u)
+
+    def step(self, nsteps=1):
+        empp_step(self.h, nsteps)
+
+    def fields_at(self, t, x, self_index=None, want_kstar=False):
+        return empp_fields_at(self.h, t, x, self.n, self_index, want_kstar)
+
+    def state(self):
+        return empp_get_state(self.h, self.n)
+
+    def history(self):
+        return empp_get_history(self.h, self.n, self.depth)
+
+    def fields(self):
+        return empp_get_fields(self.h, self.n)
+
+    def diag(self):
+        return empp_get_diag(self.h)
+
+    def set_counting(self, enable=True):
+        empp_set_counting(self.h, enable)
+
+    def counters(self):
+        return empp_get_counters(self.h)
+
+    def sync(self):
+        empp_sync(self.h)
+
+    def set_mode(self, precision, guess):
+        empp_set_mode(self.h, precision, guess)

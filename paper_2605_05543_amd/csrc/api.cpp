@@ -1,0 +1,780 @@
+// api.cpp -- the C ABI of libempp.so (declared in include/empp.h): context
+// and workspace management, argument validation, kernel launches on the
+// context's stream, and host read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "empp.h"
+#include "empp_dev.h"
+
+namespace empp {
+hipError_t launch_pair_fp64(const PairParams &p, hipStream_t stream, bool kstar, bool count);
+hipError_t launch_pair_mixed(const PairParams &p, hipStream_t stream, bool kstar, bool count);
+hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, double *E, double *B, hipStream_t s);
+hipError_t launch_push(const PushParams &p, hipStream_t s);
+hipError_t launch_init_straight(double4 *rw, double4 *rv, double *T, const double *r, const double *u, int64_t N,
+                                int D, double t0, double dt, hipStream_t s);
+hipError_t launch_history_to_ring(const double *w, const double *v, double4 *rw, double4 *rv, int64_t N, int D,
+                                  hipStream_t s);
+hipError_t launch_ring_to_history(const double4 *rw, const double4 *rv, double *w, double *v, int64_t N, int D,
+                                  int head, hipStream_t s);
+hipError_t launch_newest_positions(const double4 *rw, double *r, int64_t N, int D, int head, hipStream_t s);
+hipError_t launch_diag(const double4 *rw, const double *u, int64_t N, int D, int head, double *out, hipStream_t s);
+}  // namespace empp
+
+using namespace empp;
+
+namespace empp {
+extern const bool kHaveMixed;
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+empp_status fail(empp_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(EMPP_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+    } while (0)
+
+constexpr uint64_t kAlign = 256;
+
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, total;
+};
+
+int tile_for_depth(int D) { return std::max(1, 2048 / D); }
+
+int splits_for(const empp_config &c)
+{
+    if (c.source_splits > 0)
+        return std::min(c.source_splits, kMaxSplits);
+    int64_t bx = (c.n + kBlock - 1) / kBlock;
+    int tile = tile_for_depth(c.depth);
+    int64_t want = (2048 + bx - 1) / bx;
+    int64_t maxs = std::max<int64_t>(1, c.n / (4 * tile));
+    int64_t s = std::min(want, maxs);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplits));
+}
+
+Layout layout_for(const empp_config &c)
+{
+    Layout L{};
+    uint64_t N = (uint64_t)c.n, D = (uint64_t)c.depth;
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.ring_w = take(N * D * sizeof(double4));
+    L.ring_v = take(N * D * sizeof(double4));
+    L.T = take(D * sizeof(double));
+    L.u = take(3 * N * sizeof(double));
+    L.E = take(3 * N * sizeof(double));
+    L.B = take(3 * N * sizeof(double));
+    L.part = take((uint64_t)splits_for(c) * 12 * N * sizeof(double));
+    L.err = take(2 * sizeof(unsigned long long));
+    L.counters = take(8 * sizeof(unsigned long long));
+    L.diag = take(((N + kBlock - 1) / kBlock) * 7 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+empp_status validate(const empp_config *c)
+{
+    if (!c)
+        return fail(EMPP_EINVAL, "config is NULL");
+    if (c->n < 2)
+        return fail(EMPP_EINVAL, "n = %lld: need at least 2 particles", (long long)c->n);
+    if (c->n > (int64_t)1 << 31)
+        return fail(EMPP_EINVAL, "n = %lld exceeds 2^31", (long long)c->n);
+    if (c->depth < 2 || c->depth > 4096)
+        return fail(EMPP_EINVAL, "depth = %d: need 2 <= D <= 4096", c->depth);
+    if (!(c->dt > 0.0) || !std::isfinite(c->dt))
+        return fail(EMPP_EINVAL, "dt must be positive and finite");
+    if (!(c->m > 0.0) || !std::isfinite(c->m) || !std::isfinite(c->q))
+        return fail(EMPP_EINVAL, "mass must be positive, charge finite");
+    if (c->ext_field != 0 && c->ext_field != 1)
+        return fail(EMPP_EINVAL, "ext_field must be 0 or 1");
+    if (c->ext_field == 1 && (!std::isfinite(c->dipole_b0) || !(c->dipole_re > 0.0)))
+        return fail(EMPP_EINVAL, "dipole parameters invalid");
+    if (c->precision != EMPP_FP64 && c->precision != EMPP_MIXED)
+        return fail(EMPP_EINVAL, "unknown precision %d", c->precision);
+    if (c->precision == EMPP_MIXED && !kHaveMixed)
+        return fail(EMPP_EUNSUPPORTED, "mixed precision is not built");
+    if (c->guess < 0 || c->guess > 2)
+        return fail(EMPP_EINVAL, "unknown guess mode %d", c->guess);
+    return EMPP_OK;
+}
+
+bool all_finite(const double *a, uint64_t n)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i]))
+            return false;
+    return true;
+}
+
+}  // namespace
+
+struct empp_ctx {
+    empp_config cfg{};
+    Layout L{};
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    bool owns_ws = false;
+    int nsplit = 1;
+    int tile = 1;
+    // state
+    bool have_bunch = false;
+    bool have_history = false;
+    bool handed_off = false;
+    bool counting = false;
+    int head = 0;
+    int64_t step = 0;
+    double t_origin = 0.0;  // T of step 0
+    double t_now = 0.0;
+    std::vector<double> r0, u0;  // bunch before the history is built
+
+    template <typename Tp>
+    Tp *at(uint64_t off) const { return reinterpret_cast<Tp *>(ws + off); }
+    double4 *ring_w() const { return at<double4>(L.ring_w); }
+    double4 *ring_v() const { return at<double4>(L.ring_v); }
+    double *T() const { return at<double>(L.T); }
+    double *u() const { return at<double>(L.u); }
+    double *E() const { return at<double>(L.E); }
+    double *B() const { return at<double>(L.B); }
+    double *part() const { return at<double>(L.part); }
+    unsigned long long *err() const { return at<unsigned long long>(L.err); }
+    unsigned long long *counters() const { return at<unsigned long long>(L.counters); }
+    double *diag() const { return at<double>(L.diag); }
+};
+
+namespace {
+
+empp_status set_device(empp_ctx *ctx)
+{
+    HIP_TRY(hipSetDevice(ctx->cfg.device));
+    return EMPP_OK;
+}
+
+empp_status reset_err(empp_ctx *ctx)
+{
+    unsigned long long init[2] = {~0ull, 0ull};
+    HIP_TRY(hipMemcpyAsync(ctx->err(), init, sizeof init, hipMemcpyHostToDevice, ctx->stream));
+    return EMPP_OK;
+}
+
+empp_status check_err(empp_ctx *ctx)
+{
+    unsigned long long h[2];
+    HIP_TRY(hipMemcpyAsync(h, ctx->err(), sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (h[1] != 0) {
+        long long a = (long long)(h[0] >> 32), j = (long long)(h[0] & 0xffffffffull);
+        empp_status st = reset_err(ctx);
+        if (st != EMPP_OK)
+            return st;
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return fail(EMPP_ENUMERIC, "%s at target %lld, source %lld",
+                    (h[1] & kErrDiscriminant) ? "negative discriminant" : "coincident particles (eta = 0)", a, j);
+    }
+    return EMPP_OK;
+}
+
+PairParams pair_params(empp_ctx *ctx)
+{
+    PairParams p{};
+    p.ring_w = ctx->ring_w();
+    p.ring_v = ctx->ring_v();
+    p.T = ctx->T();
+    p.n_src = ctx->cfg.n;
+    p.D = ctx->cfg.depth;
+    p.head = ctx->head;
+    p.t = ctx->t_now;
+    const double c = kC_LIGHT;
+    const double eps0 = 1.0 / (kMU0 * c * c);
+    p.kq = ctx->cfg.q / (4.0 * M_PI * eps0);
+    p.nsplit = ctx->nsplit;
+    p.src_per_split = (ctx->cfg.n + ctx->nsplit - 1) / ctx->nsplit;
+    p.tile = ctx->tile;
+    p.part = ctx->part();
+    p.err = ctx->err();
+    p.counters = ctx->counters();
+    p.guess = ctx->cfg.guess;
+    p.dt = ctx->cfg.dt;
+    return p;
+}
+
+hipError_t launch_pair(empp_ctx *ctx, const PairParams &p, bool kstar)
+{
+    if (ctx->cfg.precision == EMPP_MIXED)
+        return launch_pair_mixed(p, ctx->stream, kstar, ctx->counting);
+    return launch_pair_fp64(p, ctx->stream, kstar, ctx->counting);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *empp_last_error(void) { return g_last_error.c_str(); }
+
+empp_status empp_workspace_size(const empp_config *cfg, uint64_t *bytes)
+{
+    empp_status st = validate(cfg);
+    if (st != EMPP_OK)
+        return st;
+    if (!bytes)
+        return fail(EMPP_EINVAL, "bytes is NULL");
+    *bytes = layout_for(*cfg).total;
+    return EMPP_OK;
+}
+
+empp_status empp_create(const empp_config *cfg, empp_ctx **out)
+{
+    if (!out)
+        return fail(EMPP_EINVAL, "out is NULL");
+    *out = nullptr;
+    empp_status st = validate(cfg);
+    if (st != EMPP_OK)
+        return st;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (cfg->device < 0 || cfg->device >= ndev)
+        return fail(EMPP_EINVAL, "device %d not present (%d devices)", cfg->device, ndev);
+    empp_ctx *ctx = new (std::nothrow) empp_ctx();
+    if (!ctx)
+        return fail(EMPP_ENOMEM, "host allocation failed");
+    ctx->cfg = *cfg;
+    ctx->L = layout_for(*cfg);
+    ctx->nsplit = splits_for(*cfg);
+    ctx->tile = tile_for_depth(cfg->depth);
+    ctx->stream = (hipStream_t)cfg->stream;
+    if ((st = set_device(ctx)) != EMPP_OK) {
+        delete ctx;
+        return st;
+    }
+    if (cfg->workspace) {
+        if (cfg->workspace_bytes < ctx->L.total || ((uintptr_t)cfg->workspace % kAlign) != 0) {
+            delete ctx;
+            return fail(EMPP_EINVAL, "workspace too small (%llu < %llu) or not 256-byte aligned",
+                        (unsigned long long)cfg->workspace_bytes, (unsigned long long)ctx->L.total);
+        }
+        ctx->ws = (char *)cfg->workspace;
+    } else {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, ctx->L.total);
+        if (e != hipSuccess) {
+            delete ctx;
+            return fail(EMPP_ENOMEM, "hipMalloc(%llu) failed: %s", (unsigned long long)ctx->L.total,
+                        hipGetErrorString(e));
+        }
+        ctx->ws = (char *)p;
+        ctx->owns_ws = true;
+    }
+    if ((st = reset_err(ctx)) != EMPP_OK || (st = empp_set_counting(ctx, 0)) != EMPP_OK) {
+        empp_destroy(ctx);
+        return st;
+    }
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        empp_destroy(ctx);
+        return fail(EMPP_EDEVICE, "stream synchronise failed: %s", hipGetErrorString(e));
+    }
+    *out = ctx;
+    return EMPP_OK;
+}
+
+void empp_destroy(empp_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipSetDevice(ctx->cfg.device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->owns_ws && ctx->ws)
+        (void)hipFree(ctx->ws);
+    delete ctx;
+}
+
+empp_status empp_init_bunch(empp_ctx *ctx, const double *r, const double *u, double t0)
+{
+    if (!ctx || !r || !u)
+        return fail(EMPP_EINVAL, "NULL argument");
+    const uint64_t n3 = 3 * (uint64_t)ctx->cfg.n;
+    if (!all_finite(r, n3) || !all_finite(u, n3) || !std::isfinite(t0))
+        return fail(EMPP_EINVAL, "non-finite bunch value");
+    ctx->r0.assign(r, r + n3);
+    ctx->u0.assign(u, u + n3);
+    ctx->t_origin = t0;
+    ctx->have_bunch = true;
+    ctx->have_history = false;
+    ctx->handed_off = false;
+    return EMPP_OK;
+}
+
+empp_status empp_init_history_straight(empp_ctx *ctx)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    if (!ctx->have_bunch)
+        return fail(EMPP_ESTATE, "init_history_straight before init_bunch");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    const int64_t N = ctx->cfg.n;
+    const int D = ctx->cfg.depth;
+    // r is staged in the partials buffer (>= 12 N doubles), u goes to u.
+    double *r_dev = ctx->part();
+    HIP_TRY(hipMemcpyAsync(r_dev, ctx->r0.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->u(), ctx->u0.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(launch_init_straight(ctx->ring_w(), ctx->ring_v(), ctx->T(), r_dev, ctx->u(), N, D, ctx->t_origin,
+                                 ctx->cfg.dt, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->E(), 0, 3 * N * sizeof(double), ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->B(), 0, 3 * N * sizeof(double), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->head = D - 1;
+    ctx->step = 0;
+    ctx->t_now = ctx->t_origin;  // t0 + 0 * dt
+    ctx->have_history = true;
+    ctx->handed_off = false;
+    return EMPP_OK;
+}
+
+empp_status empp_set_history(empp_ctx *ctx, int32_t nslots, const double *T, const double *w, const double *v,
+                             const double *u)
+{
+    if (!ctx || !T || !w || !v || !u)
+        return fail(EMPP_EINVAL, "NULL argument");
+    const int64_t N = ctx->cfg.n;
+    const int D = ctx->cfg.depth;
+    if (nslots != D)
+        return fail(EMPP_EINVAL, "nslots %d != depth %d", nslots, D);
+    const uint64_t tot = 3 * (uint64_t)N * D;
+    if (!all_finite(T, D) || !all_finite(w, tot) || !all_finite(v, tot) || !all_finite(u, 3 * (uint64_t)N))
+        return fail(EMPP_EINVAL, "non-finite history value");
+    for (int s = 1; s < D; ++s)
+        if (!(T[s] > T[s - 1]))
+            return fail(EMPP_EINVAL, "slot times not strictly increasing at slot %d", s);
+    const double c2 = kC_LIGHT * kC_LIGHT;
+    for (int s = 0; s < D; ++s)
+        for (int64_t i = 0; i < N; ++i) {
+            const double *vs = v + (uint64_t)s * 3 * N;
+            double v2 = vs[i] * vs[i] + vs[N + i] * vs[N + i] + vs[2 * N + i] * vs[2 * N + i];
+            if (!(v2 < c2))
+                return fail(EMPP_EINVAL, "stored speed >= c (slot %d, particle %lld)", s, (long long)i);
+        }
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    double *tmp = nullptr;
+    hipError_t e = hipMalloc((void **)&tmp, 2 * tot * sizeof(double));
+    if (e != hipSuccess)
+        return fail(EMPP_ENOMEM, "hipMalloc for history upload failed: %s", hipGetErrorString(e));
+    auto body = [&]() -> empp_status {
+        HIP_TRY(hipMemcpyAsync(tmp, w, tot * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(tmp + tot, v, tot * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(launch_history_to_ring(tmp, tmp + tot, ctx->ring_w(), ctx->ring_v(), N, D, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->T(), T, D * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->u(), u, 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipMemsetAsync(ctx->E(), 0, 3 * N * sizeof(double), ctx->stream));
+        HIP_TRY(hipMemsetAsync(ctx->B(), 0, 3 * N * sizeof(double), ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return EMPP_OK;
+    };
+    st = body();
+    (void)hipFree(tmp);
+    if (st != EMPP_OK)
+        return st;
+    ctx->head = D - 1;
+    ctx->step = 0;
+    ctx->t_origin = T[D - 1];
+    ctx->t_now = T[D - 1];
+    ctx->have_bunch = true;
+    ctx->have_history = true;
+    ctx->handed_off = false;
+    return EMPP_OK;
+}
+
+empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    if (nsteps < 0)
+        return fail(EMPP_EINVAL, "nsteps < 0");
+    if (!ctx->have_history)
+        return fail(EMPP_ESTATE, "step before the history is initialised");
+    if (ctx->handed_off)
+        return fail(EMPP_ESTATE, "step after handoff (use transport)");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    const int64_t N = ctx->cfg.n;
+    const double c = kC_LIGHT;
+    (void)c;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        PairParams p = pair_params(ctx);
+        p.x = nullptr;
+        p.self_index = nullptr;
+        p.m = N;
+        p.kstar = nullptr;
+        HIP_TRY(launch_pair(ctx, p, false));
+        PushParams q{};
+        q.ring_w = ctx->ring_w();
+        q.ring_v = ctx->ring_v();
+        q.T = ctx->T();
+        q.u = ctx->u();
+        q.E = ctx->E();
+        q.B = ctx->B();
+        q.part = ctx->part();
+        q.nsplit = ctx->nsplit;
+        q.N = N;
+        q.D = ctx->cfg.depth;
+        q.head = ctx->head;
+        q.dt = ctx->cfg.dt;
+        q.t_next = ctx->t_origin + (double)(ctx->step + 1) * ctx->cfg.dt;
+        q.eps = ctx->cfg.q * ctx->cfg.dt / (2.0 * ctx->cfg.m);
+        q.ext_field = ctx->cfg.ext_field;
+        q.dip_k = ctx->cfg.dipole_b0 * ctx->cfg.dipole_re * ctx->cfg.dipole_re * ctx->cfg.dipole_re;
+        q.self_field = 1;
+        HIP_TRY(launch_push(q, ctx->stream));
+        ctx->head = ctx->head + 1 == ctx->cfg.depth ? 0 : ctx->head + 1;
+        ctx->step += 1;
+        ctx->t_now = q.t_next;
+    }
+    return EMPP_OK;
+}
+
+static empp_status fields_dev_impl(empp_ctx *ctx, int64_t m, const double *x_dev, const int64_t *self_dev,
+                                   double *E_dev, double *B_dev, int32_t *kstar_dev)
+{
+    const int64_t N = ctx->cfg.n;
+    // targets go through in chunks of at most N (the partials buffer's size)
+    for (int64_t a0 = 0; a0 < m; a0 += N) {
+        int64_t mc = std::min<int64_t>(N, m - a0);
+        // x for the chunk must be a [3][mc] array: chunking needs a copy
+        const double *xc = x_dev;
+        double *tmpx = nullptr;
+        if (m > N) {
+            HIP_TRY(hipMalloc((void **)&tmpx, 3 * mc * sizeof(double)));
+            for (int k = 0; k < 3; ++k)
+                HIP_TRY(hipMemcpyAsync(tmpx + k * mc, x_dev + k * m + a0, mc * sizeof(double),
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+            xc = tmpx;
+        }
+        PairParams p = pair_params(ctx);
+        p.x = xc;
+        p.self_index = self_dev ? self_dev + a0 : nullptr;
+        p.m = mc;
+        p.kstar = kstar_dev ? kstar_dev + a0 * N : nullptr;
+        hipError_t e = launch_pair(ctx, p, kstar_dev != nullptr);
+        double *Ec = E_dev, *Bc = B_dev;
+        double *tmpo = nullptr;
+        if (e == hipSuccess && m > N) {
+            e = hipMalloc((void **)&tmpo, 6 * mc * sizeof(double));
+            Ec = tmpo;
+            Bc = tmpo + 3 * mc;
+        }
+        if (e == hipSuccess)
+            e = launch_merge_fields(ctx->part(), ctx->nsplit, mc, Ec, Bc, ctx->stream);
+        if (e == hipSuccess && m > N) {
+            for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+                e = hipMemcpyAsync(E_dev + k * m + a0, Ec + k * mc, mc * sizeof(double), hipMemcpyDeviceToDevice,
+                                   ctx->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(B_dev + k * m + a0, Bc + k * mc, mc * sizeof(double),
+                                       hipMemcpyDeviceToDevice, ctx->stream);
+            }
+            (void)hipStreamSynchronize(ctx->stream);
+        }
+        if (tmpx)
+            (void)hipFree(tmpx);
+        if (tmpo)
+            (void)hipFree(tmpo);
+        if (e != hipSuccess)
+            return fail(EMPP_EDEVICE, "fields_at: %s", hipGetErrorString(e));
+    }
+    return EMPP_OK;
+}
+
+static empp_status fields_precheck(empp_ctx *ctx, double t, int64_t m)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    if (!ctx->have_history)
+        return fail(EMPP_ESTATE, "fields_at before the history is initialised");
+    if (ctx->handed_off)
+        return fail(EMPP_ESTATE, "fields_at after handoff");
+    if (m < 0)
+        return fail(EMPP_EINVAL, "m < 0");
+    if (t != ctx->t_now)
+        return fail(EMPP_EINVAL, "t = %.17g is not the present time %.17g", t, ctx->t_now);
+    return set_device(ctx);
+}
+
+empp_status empp_fields_at_dev(empp_ctx *ctx, double t, int64_t m, const double *x_dev, const int64_t *self_dev,
+                               double *E_dev, double *B_dev, int32_t *kstar_dev)
+{
+    empp_status st = fields_precheck(ctx, t, m);
+    if (st != EMPP_OK)
+        return st;
+    if (m == 0)
+        return EMPP_OK;
+    if (!x_dev || !E_dev || !B_dev)
+        return fail(EMPP_EINVAL, "NULL argument");
+    return fields_dev_impl(ctx, m, x_dev, self_dev, E_dev, B_dev, kstar_dev);
+}
+
+empp_status empp_fields_at(empp_ctx *ctx, double t, int64_t m, const double *x, const int64_t *self_index,
+                           double *E, double *B, int32_t *kstar)
+{
+    empp_status st = fields_precheck(ctx, t, m);
+    if (st != EMPP_OK)
+        return st;
+    if (m == 0)
+        return EMPP_OK;
+    if (!x || !E || !B)
+        return fail(EMPP_EINVAL, "NULL argument");
+    if (!all_finite(x, 3 * (uint64_t)m))
+        return fail(EMPP_EINVAL, "non-finite target position");
+    const int64_t N = ctx->cfg.n;
+    if (self_index)
+        for (int64_t a = 0; a < m; ++a)
+            if (self_index[a] < -1 || self_index[a] >= N)
+                return fail(EMPP_EINVAL, "self_index[%lld] out of range", (long long)a);
+    uint64_t bytes = 3 * m * sizeof(double) * 3 + (self_index ? m * sizeof(int64_t) : 0) +
+                     (kstar ? (uint64_t)m * N * sizeof(int32_t) : 0) + 4 * kAlign;
+    char *tmp = nullptr;
+    hipError_t e = hipMalloc((void **)&tmp, bytes);
+    if (e != hipSuccess)
+        return fail(EMPP_ENOMEM, "hipMalloc(%llu) for fields_at failed", (unsigned long long)bytes);
+    uint64_t o = 0;
+    auto take = [&](uint64_t b) {
+        char *p = tmp + o;
+        o = align_up(o + b);
+        return p;
+    };
+    double *xd = (double *)take(3 * m * sizeof(double));
+    double *Ed = (double *)take(3 * m * sizeof(double));
+    double *Bd = (double *)take(3 * m * sizeof(double));
+    int64_t *sd = self_index ? (int64_t *)take(m * sizeof(int64_t)) : nullptr;
+    int32_t *kd = kstar ? (int32_t *)take((uint64_t)m * N * sizeof(int32_t)) : nullptr;
+    auto body = [&]() -> empp_status {
+        HIP_TRY(hipMemcpyAsync(xd, x, 3 * m * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        if (sd)
+            HIP_TRY(hipMemcpyAsync(sd, self_index, m * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        empp_status s2 = fields_dev_impl(ctx, m, xd, sd, Ed, Bd, kd);
+        if (s2 != EMPP_OK)
+            return s2;
+        HIP_TRY(hipMemcpyAsync(E, Ed, 3 * m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(B, Bd, 3 * m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        if (kd)
+            HIP_TRY(hipMemcpyAsync(kstar, kd, (uint64_t)m * N * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        return check_err(ctx);
+    };
+    st = body();
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(tmp);
+    return st;
+}
+
+empp_status empp_sync(empp_ctx *ctx)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    return check_err(ctx);
+}
+
+empp_status empp_get_state(empp_ctx *ctx, double *r, double *u, double *t, int64_t *step)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    if (!ctx->have_history)
+        return fail(EMPP_ESTATE, "no state yet");
+    empp_status st = empp_sync(ctx);
+    if (st != EMPP_OK)
+        return st;
+    const int64_t N = ctx->cfg.n;
+    if (r) {
+        double *tmp = nullptr;
+        HIP_TRY(hipMalloc((void **)&tmp, 3 * N * sizeof(double)));
+        hipError_t e = launch_newest_positions(ctx->ring_w(), tmp, N, ctx->cfg.depth, ctx->head, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(r, tmp, 3 * N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(ctx->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess)
+            return fail(EMPP_EDEVICE, "get_state: %s", hipGetErrorString(e));
+    }
+    if (u) {
+        HIP_TRY(hipMemcpyAsync(u, ctx->u(), 3 * N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    if (t)
+        *t = ctx->t_now;
+    if (step)
+        *step = ctx->step;
+    return EMPP_OK;
+}
+
+empp_status empp_get_history(empp_ctx *ctx, double *T, double *w, double *v)
+{
+    if (!ctx || !T || !w || !v)
+        return fail(EMPP_EINVAL, "NULL argument");
+    if (!ctx->have_history || ctx->handed_off)
+        return fail(EMPP_ESTATE, "no history");
+    empp_status st = empp_sync(ctx);
+    if (st != EMPP_OK)
+        return st;
+    const int64_t N = ctx->cfg.n;
+    const int D = ctx->cfg.depth;
+    const uint64_t tot = 3 * (uint64_t)N * D;
+    double *tmp = nullptr;
+    HIP_TRY(hipMalloc((void **)&tmp, 2 * tot * sizeof(double)));
+    hipError_t e = launch_ring_to_history(ctx->ring_w(), ctx->ring_v(), tmp, tmp + tot, N, D, ctx->head, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w, tmp, tot * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(v, tmp + tot, tot * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    std::vector<double> Tp(D);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(Tp.data(), ctx->T(), D * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess)
+        return fail(EMPP_EDEVICE, "get_history: %s", hipGetErrorString(e));
+    for (int s = 0; s < D; ++s) {
+        int ph = ctx->head - (D - 1 - s);
+        ph += ph < 0 ? D : 0;
+        T[s] = Tp[ph];
+    }
+    return EMPP_OK;
+}
+
+empp_status empp_get_fields(empp_ctx *ctx, double *E, double *B)
+{
+    if (!ctx || !E || !B)
+        return fail(EMPP_EINVAL, "NULL argument");
+    if (!ctx->have_history)
+        return fail(EMPP_ESTATE, "no state yet");
+    empp_status st = empp_sync(ctx);
+    if (st != EMPP_OK)
+        return st;
+    const int64_t N = ctx->cfg.n;
+    HIP_TRY(hipMemcpyAsync(E, ctx->E(), 3 * N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(B, ctx->B(), 3 * N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return EMPP_OK;
+}
+
+empp_status empp_get_diag(empp_ctx *ctx, empp_diag *out)
+{
+    if (!ctx || !out)
+        return fail(EMPP_EINVAL, "NULL argument");
+    if (!ctx->have_history)
+        return fail(EMPP_ESTATE, "no state yet");
+    empp_status st = empp_sync(ctx);
+    if (st != EMPP_OK)
+        return st;
+    const int64_t N = ctx->cfg.n;
+    const int64_t nb = (N + kBlock - 1) / kBlock;
+    HIP_TRY(launch_diag(ctx->ring_w(), ctx->u(), N, ctx->cfg.depth, ctx->head, ctx->diag(), ctx->stream));
+    std::vector<double> h(nb * 7);
+    double4 ref;
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx->diag(), nb * 7 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(&ref, ctx->ring_w() + ctx->head, sizeof ref, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    double s[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t b = 0; b < nb; ++b)
+        for (int k = 0; k < 7; ++k)
+            s[k] += h[b * 7 + k];
+    const double inv = 1.0 / (double)N;
+    const double refc[3] = {ref.x, ref.y, ref.z};
+    for (int k = 0; k < 3; ++k) {
+        double mean = s[k] * inv;
+        double var = s[3 + k] * inv - mean * mean;
+        out->sigma[k] = std::sqrt(std::max(var, 0.0));
+        out->centroid[k] = refc[k] + mean;
+    }
+    out->sigma_xy = 0.5 * (out->sigma[0] + out->sigma[1]);
+    out->mean_kinetic = s[6] * inv * ctx->cfg.m * kC_LIGHT * kC_LIGHT;
+    out->t = ctx->t_now;
+    out->step = ctx->step;
+    return EMPP_OK;
+}
+
+empp_status empp_set_counting(empp_ctx *ctx, int32_t enable)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    ctx->counting = enable != 0;
+    HIP_TRY(hipMemsetAsync(ctx->counters(), 0, 8 * sizeof(unsigned long long), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return EMPP_OK;
+}
+
+empp_status empp_get_counters(empp_ctx *ctx, empp_counters *out)
+{
+    if (!ctx || !out)
+        return fail(EMPP_EINVAL, "NULL argument");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    unsigned long long h[8];
+    HIP_TRY(hipMemcpyAsync(h, ctx->counters(), sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    out->pairs = h[0];
+    out->before = h[1];
+    out->probes = h[2];
+    out->rescues = h[3];
+    out->fallbacks = h[4];
+    return EMPP_OK;
+}
+
+empp_status empp_set_mode(empp_ctx *ctx, int32_t precision, int32_t guess)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    empp_config c = ctx->cfg;
+    c.precision = precision;
+    c.guess = guess;
+    empp_status st = validate(&c);
+    if (st != EMPP_OK)
+        return st;
+    ctx->cfg.precision = precision;
+    ctx->cfg.guess = guess;
+    return EMPP_OK;
+}
+
+}  // extern "C"

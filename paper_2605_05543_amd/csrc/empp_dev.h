@@ -1,0 +1,111 @@
+// empp_dev.h -- device-side types and helpers shared by the HIP kernels of
+// libempp.so.  gfx950 only; compiled with hipcc --offload-arch=gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace empp {
+
+// CODATA 2018 (c, e, m_e exact or recommended; mu0 recommended).
+constexpr double kC_LIGHT = 299792458.0;
+constexpr double kMU0 = 1.25663706212e-6;
+
+constexpr int kBlock = 256;        // threads per block of the pair kernels
+constexpr int kMaxSplits = 1024;   // source chunks of one launch
+
+// History layout in HBM (library-owned workspace):
+//   ring_w[j * D + p] = {x, y, z, 0}     position of source j at physical slot p
+//   ring_v[j * D + p] = {vx, vy, vz, 0}  velocity leaving that slot
+//   T[p]                                  slot time
+// Slot p holds logical slot "back" b (0 = newest) when p = (head - b) mod D.
+// A source's whole history is one contiguous 32*D-byte block, so a block
+// of targets stages it into LDS with straight coalesced loads.
+
+struct PairParams {
+    const double4 *ring_w;
+    const double4 *ring_v;
+    const double *T;
+    int64_t n_src;      // sources N
+    int32_t D;
+    int32_t head;       // physical index of the newest slot
+    double t;           // present time (== T[head])
+    double kq;          // Coulomb constant times source charge
+    // targets: external points x[3][m] (x != nullptr) or the particles'
+    // newest positions (x == nullptr, then target a is particle a and the
+    // pair (a, a) is skipped).
+    const double *x;
+    const int64_t *self_index;  // external mode only, may be null
+    int64_t m;
+    int64_t src_per_split;
+    int32_t nsplit;
+    int32_t tile;               // sources staged per LDS tile
+    double *part;               // [nsplit][12][m] partial (sum, comp)
+    int32_t *kstar;             // [m][N] or null
+    unsigned long long *err;    // [2]: first failing pair, status bits
+    unsigned long long *counters;  // [5] pairs, before, probes, rescues, fallbacks
+    // surrogate / guided search
+    int32_t guess;
+    float dt_inv_f;
+    double dt;
+    const void *mlp;            // packed bf16 network (mixed path)
+    double sigma_ref_inv;
+};
+
+struct PushParams {
+    double4 *ring_w;
+    double4 *ring_v;
+    double *T;
+    double *u;          // [3][N]
+    double *E;          // [3][N] self-field of the step (output of the merge)
+    double *B;
+    const double *part; // [nsplit][12][N]
+    int32_t nsplit;
+    int64_t N;
+    int32_t D;
+    int32_t head;       // newest physical slot before the push
+    double dt;
+    double t_next;      // time of the new slot
+    double eps;         // q dt / (2 m)
+    int32_t ext_field;
+    double dip_k;       // b0 * re^3: (mu0/4pi) M0 for the centred dipole
+    int32_t self_field; // 0: stage-II transport (E = 0, B = B_geo only)
+};
+
+// Error word: err[0] = (target << 32 | source) of the lowest failing pair
+// (atomicMin), err[1] = OR of status bits.
+constexpr unsigned long long kErrCoincident = 1ull;
+constexpr unsigned long long kErrDiscriminant = 2ull;
+
+__device__ inline void report_error(unsigned long long *err, int64_t a, int64_t j,
+                                    unsigned long long bit)
+{
+    unsigned long long key = ((unsigned long long)(uint32_t)a << 32) | (uint32_t)j;
+    atomicMin(&err[0], key);
+    atomicOr(&err[1], bit);
+}
+
+// Reciprocal of a positive normal double: hardware estimate plus two
+// Newton-Raphson steps (the estimate is good to ~2^-29, each step squares
+// the relative error), accurate to about one unit in the last place.
+__device__ inline double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    return r;
+}
+
+// Neumaier accumulation of x into (s, c).
+__device__ inline void neumaier(double &s, double &c, double x)
+{
+    double t = s + x;
+    double big = fabs(s) >= fabs(x) ? s : x;
+    double small = fabs(s) >= fabs(x) ? x : s;
+    c += (big - t) + small;
+    s = t;
+}
+
+}  // namespace empp

@@ -1,0 +1,140 @@
+// pair_common.h -- light-cone sign test and history searches used by the
+// pair kernels (Sec. 2.2 of arXiv 2605.05543).
+#pragma once
+
+#include "empp_dev.h"
+
+namespace empp {
+
+// Staged history record of one source at one logical slot:
+// {x, y, z, L} with L = c (t - T_k) the light distance back to the slot.
+// The sign test f_k > 0 <=> L*L > (dx*dx + dy*dy) + dz*dz is evaluated
+// without fused multiply-adds and in this association, so it rounds
+// exactly like a plain IEEE evaluation of the same expression.
+__device__ inline bool lightcone_positive(double4 rec, double rx, double ry, double rz)
+{
+#pragma clang fp contract(off)
+    double dx = rx - rec.x;
+    double dy = ry - rec.y;
+    double dz = rz - rec.z;
+    double L = rec.w;
+    return L * L > (dx * dx + dy * dy) + dz * dz;
+}
+
+// Bisection of the paper: test the oldest sample first (if it is not
+// inside the past light cone the retarded time precedes the history);
+// otherwise halve [oldest, newest] until the bracket is one step wide.
+// Works in "back" offsets b (0 = newest).  Because f_k decreases strictly
+// along the history, the bracket found is the unique one:
+// b* = min { b : f_b > 0 }.  Returns b* or -1 (before the history).
+template <typename Rec>
+__device__ inline int search_bisect(Rec rec, int D, double rx, double ry, double rz, int &probes)
+{
+    probes += 1;
+    if (!lightcone_positive(rec(D - 1), rx, ry, rz))
+        return -1;
+    int lo = D - 1, hi = 0;  // f(lo) > 0, f(hi) <= 0 (newest: t - T = 0)
+    while (lo - hi > 1) {
+        int mid = (lo + hi) >> 1;
+        probes += 1;
+        if (lightcone_positive(rec(mid), rx, ry, rz))
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Guided search: start at a guessed back offset g, confirm with the
+// neighbouring sample, otherwise gallop (1, 2, 4, ... slots) towards the
+// bracket and bisect inside the last gallop step.  Reaches the same b* as
+// search_bisect for any guess.  A non-finite guess or more than
+// max_gallop doublings falls back to plain bisection of what is left
+// (counted in fallbacks).
+template <typename Rec>
+__device__ inline int search_guided(Rec rec, int D, double rx, double ry, double rz, float guess,
+                                    int max_gallop, int &probes, int &fallback)
+{
+    int lo, hi;  // f(lo) > 0 (older side), f(hi) <= 0 (newer side)
+    if (!(guess == guess) || !(fabsf(guess) < 1e9f)) {
+        fallback = 1;
+        return search_bisect(rec, D, rx, ry, rz, probes);
+    }
+    int g = (int)ceilf(guess);
+    g = g < 1 ? 1 : (g > D - 1 ? D - 1 : g);
+    probes += 1;
+    if (lightcone_positive(rec(g), rx, ry, rz)) {
+        lo = g;
+        hi = 0;
+        int step = 1, n = 0;
+        while (true) {
+            int cand = lo - step;
+            if (cand <= 0)
+                break;  // hi = 0 (newest sample is never inside)
+            probes += 1;
+            if (lightcone_positive(rec(cand), rx, ry, rz)) {
+                lo = cand;
+            } else {
+                hi = cand;
+                break;
+            }
+            step <<= 1;
+            if (++n > max_gallop) {
+                fallback = 1;
+                break;  // bisect the rest of [hi=0, lo]
+            }
+        }
+    } else {
+        hi = g;
+        lo = -1;
+        int step = 1, n = 0;
+        while (true) {
+            int cand = hi + step;
+            if (cand >= D - 1 || n >= max_gallop) {
+                if (n >= max_gallop)
+                    fallback = 1;
+                probes += 1;
+                if (lightcone_positive(rec(D - 1), rx, ry, rz))
+                    lo = D - 1;
+                else
+                    return -1;
+                break;
+            }
+            probes += 1;
+            if (lightcone_positive(rec(cand), rx, ry, rz)) {
+                lo = cand;
+                break;
+            }
+            hi = cand;
+            step <<= 1;
+            ++n;
+        }
+    }
+    while (lo - hi > 1) {
+        int mid = (lo + hi) >> 1;
+        probes += 1;
+        if (lightcone_positive(rec(mid), rx, ry, rz))
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Closed-form look-back of a source coasting with velocity v from its
+// newest position: with R = r - w_n and beta = v/c, the light distance
+// s = c (t - t_r) solves (1 - beta^2) s^2 - 2 (R.beta) s - R^2 = 0.
+// Returns s / (c dt), the look-back in steps.
+__device__ inline float ballistic_steps(double Rx, double Ry, double Rz, double4 v, float inv_cdt)
+{
+    float rx = (float)Rx, ry = (float)Ry, rz = (float)Rz;
+    const float ic = (float)(1.0 / kC_LIGHT);
+    float bx = (float)v.x * ic, by = (float)v.y * ic, bz = (float)v.z * ic;
+    float rb = rx * bx + ry * by + rz * bz;
+    float r2 = rx * rx + ry * ry + rz * rz;
+    float g2 = 1.0f - (bx * bx + by * by + bz * bz);
+    float s = (rb + sqrtf(rb * rb + g2 * r2)) / g2;
+    return s * inv_cdt;
+}
+
+}  // namespace empp

@@ -1,0 +1,209 @@
+"""GPU (HIP, through the C ABI) against the CPU oracle, FP64 path.
+
+k* must match bit for bit; fields within 1e-12 of the per-target sum of
+magnitudes and of the rms field.  Inputs come from the seeded generators
+(paper_2605_05543_amd.bunch) or from the oracle's own stepping."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_05543_amd import bunch
+from parity import assert_fields, assert_kstar
+
+pytestmark = pytest.mark.gpu
+
+Q, ME = -bunch.E_CHARGE, bunch.M_ELECTRON
+
+
+def _ctx(n, depth, dt, guess=0, precision=0, **kw):
+    from paper_2605_05543_amd._lib import Context
+
+    return Context(n=n, depth=depth, q=Q, m=ME, dt=dt, guess=guess, precision=precision, **kw)
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.get()
+
+
+@pytest.mark.parametrize("guess", [0, 2])
+@pytest.mark.parametrize("n,depth,m", [(48, 64, 300), (61, 37, 129), (300, 128, 257)])
+def test_fields_at_wiggly(orc, n, depth, m, guess):
+    """Curving sources (non-zero acceleration in history), external
+    targets spanning several LDS tiles and ragged tails."""
+    print(f"case wiggly n={n} D={depth} m={m} guess={guess}", flush=True)
+    dt = 1e-13
+    T, w, v = bunch.wiggly_history(n, depth, dt, beta=0.9, accel_rel=0.1, seed=n + depth)
+    rng = np.random.default_rng(m)
+    x = 1.5e-3 * rng.standard_normal((3, m))
+    u = np.zeros((3, n))
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], x, want_kstar=True, want_abs=True)
+    with _ctx(n, depth, dt, guess=guess) as ctx:
+        ctx.set_history(T, w, v, u)
+        E, B, k = ctx.fields_at(T[-1], x, want_kstar=True)
+    assert_kstar("wiggly", k, k0)
+    assert_fields("wiggly", E, B, E0, B0, SE, SB)
+
+
+@pytest.mark.parametrize("guess", [0, 2])
+def test_c1_initial_all_targets(orc, guess):
+    wl = bunch.C1
+    print(f"case C1 initial all targets guess={guess}", flush=True)
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    n = wl.bunch.n
+    T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], r, np.arange(n), want_kstar=True, want_abs=True)
+    with _ctx(n, wl.depth, wl.dt, guess=guess) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        Tg, wg, vg = ctx.history()
+        assert np.array_equal(Tg, T) and np.array_equal(wg, w) and np.array_equal(vg, v)
+        E, B, k = ctx.fields_at(0.0, r, np.arange(n), want_kstar=True)
+        ctx.step(1)
+        Es, Bs = ctx.fields()
+    assert_kstar("C1 init", k, k0)
+    assert_fields("C1 init fields_at", E, B, E0, B0, SE, SB)
+    assert_fields("C1 init step", Es, Bs, E0, B0, SE, SB)
+
+
+def test_c1_synchronised_steps(orc):
+    """C1 for 200 steps in the oracle; at several steps the GPU is given the
+    oracle's state, takes one step, and must reproduce the oracle's fields
+    (1e-12), k* (exact) and next state."""
+    wl = bunch.C1
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    n = wl.bunch.n
+    run = oracle.OracleRun(orc, r, u, D=wl.depth, dt=wl.dt, q=Q, mass=ME)
+    check_at = {0, 1, 7, 50, 120, 199}
+    with _ctx(n, wl.depth, wl.dt) as ctx:
+        for step in range(wl.steps):
+            if step in check_at:
+                print(f"case C1 synchronised step {step}", flush=True)
+                T, w, v, uu = run.T.copy(), run.w.copy(), run.v.copy(), run.u.copy()
+                E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], w[-1], np.arange(n), want_kstar=True,
+                                                want_abs=True)
+                ctx.set_history(T, w, v, uu)
+                _, _, k = ctx.fields_at(T[-1], w[-1], np.arange(n), want_kstar=True)
+                ctx.step(1)
+                Eg, Bg = ctx.fields()
+                rg, ug, tg, _ = ctx.state()
+                run.step(1)
+                assert_kstar(f"C1 step {step}", k, k0)
+                assert_fields(f"C1 step {step}", Eg, Bg, E0, B0, SE, SB)
+                dy = np.max(np.abs(rg - run.y))
+                du = np.max(np.abs(ug - run.u)) / np.max(np.abs(run.u))
+                print(f"   next state: max|dy| {dy:.2e} m, max|du|/|u| {du:.2e}, t {tg} vs {run.t}", flush=True)
+                assert dy < 1e-16 and du < 1e-15 and tg == run.t
+            else:
+                run.step(1)
+
+
+def test_c1_free_running(orc):
+    """Both sides run C1's 200 steps from the same initial bunch; the
+    trajectories may only drift apart by rounding."""
+    wl = bunch.C1
+    print("case C1 free running 200 steps", flush=True)
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    n = wl.bunch.n
+    run = oracle.OracleRun(orc, r, u, D=wl.depth, dt=wl.dt, q=Q, mass=ME)
+    run.step(wl.steps)
+    with _ctx(n, wl.depth, wl.dt) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        ctx.step(wl.steps)
+        rg, ug, tg, sg = ctx.state()
+        Eg, Bg = ctx.fields()
+        diag = ctx.diag()
+    sig = np.std(r, axis=1).mean()
+    dy = np.max(np.abs(rg - run.y)) / sig
+    du = np.max(np.abs(ug - run.u)) / np.max(np.abs(run.u))
+    dE = np.max(np.linalg.norm(Eg - run.E, axis=0)) / np.sqrt(np.mean(np.sum(run.E**2, 0)))
+    print(f"C1 200 steps: max|dy|/sigma {dy:.2e}, max|du|/|u| {du:.2e}, last-step field err/rms {dE:.2e}", flush=True)
+    assert sg == wl.steps and tg == run.t
+    assert dy < 1e-12 and du < 1e-13 and dE < 1e-10
+    od = run.diag()
+    for k in range(3):
+        assert abs(diag["sigma"][k] / od[k] - 1) < 1e-9
+    assert abs(diag["mean_kinetic"] / od[7] - 1) < 1e-12
+
+
+def test_c2_subset_and_invariants(orc):
+    """C2 size (N=8192, D=512): 64 seeded targets against the oracle at the
+    initial state (the launch shape the step uses), then 1000 GPU steps with
+    the history invariants checked at the end."""
+    wl = bunch.C2
+    print("case C2 subset", flush=True)
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    n = wl.bunch.n
+    sub = bunch.target_subset(n, 64, 102)
+    T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], r[:, sub], sub, want_kstar=True, want_abs=True)
+    with _ctx(n, wl.depth, wl.dt) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        _, _, k = ctx.fields_at(0.0, r[:, sub], sub, want_kstar=True)
+        ctx.step(1)
+        Es, Bs = ctx.fields()
+        assert_kstar("C2 subset", k, k0)
+        assert_fields("C2 subset (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
+        print("case C2 1000 steps", flush=True)
+        ctx.step(wl.steps - 1)
+        Tg, wg, vg = ctx.history()
+        rg, ug, tg, sg = ctx.state()
+    assert sg == wl.steps
+    seg = np.max(np.abs(wg[1:] - (wg[:-1] + vg[:-1] * np.diff(Tg)[:, None, None])))
+    g = np.sqrt(1 + (ug**2).sum(0) / bunch.C_LIGHT**2)
+    print(f"C2 after 1000 steps: segment invariant {seg:.2e} m, newest v vs u/gamma "
+          f"{np.max(np.abs(vg[-1] - ug / g)):.2e}", flush=True)
+    assert seg < 1e-17 and np.max(np.abs(vg[-1] - ug / g)) < 1e-6
+    assert np.all(np.isfinite(wg))
+
+
+def test_c3_full_size_sampled(orc):
+    """C3 size (N=65536, D=512, dipole at 3 R_E): the step's fields at 128
+    seeded targets against the oracle, and k* of those targets."""
+    wl = bunch.C3
+    print("case C3 full size sampled", flush=True)
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    n = wl.bunch.n
+    sub = bunch.target_subset(n, 128, 103)
+    T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], r[:, sub], sub, want_kstar=True, want_abs=True)
+    with _ctx(n, wl.depth, wl.dt, ext_field=1, dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        _, _, k = ctx.fields_at(0.0, r[:, sub], sub, want_kstar=True)
+        ctx.step(1)
+        Es, Bs = ctx.fields()
+    assert_kstar("C3 subset", k, k0)
+    assert_fields("C3 subset (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
+
+
+def test_errors_are_reported(orc):
+    """Host-checked and device-latched errors come back as statuses."""
+    from paper_2605_05543_amd._lib import EMPP_EINVAL, EMPP_ENUMERIC, EMPP_ESTATE, EmppError
+
+    print("case error paths", flush=True)
+    T, w, v = bunch.wiggly_history(8, 16, 1e-13, seed=3)
+    u = np.zeros((3, 8))
+    with _ctx(8, 16, 1e-13) as ctx:
+        with pytest.raises(EmppError) as ei:
+            ctx.step(1)
+        assert ei.value.status == EMPP_ESTATE
+        vbad = v.copy()
+        vbad[3, 2, 5] = 1.01 * bunch.C_LIGHT
+        with pytest.raises(EmppError) as ei:
+            ctx.set_history(T, w, vbad, u)
+        assert ei.value.status == EMPP_EINVAL
+        ctx.set_history(T, w, v, u)
+        with pytest.raises(EmppError) as ei:
+            ctx.fields_at(T[-1] + 1e-15, np.zeros((3, 1)))
+        assert ei.value.status == EMPP_EINVAL
+        # a target sitting exactly on source 4's newest position: eta = 0
+        x = w[-1][:, 4:5].copy()
+        with pytest.raises(EmppError) as ei:
+            ctx.fields_at(T[-1], x)
+        assert ei.value.status == EMPP_ENUMERIC and "source 4" in str(ei.value)
+        # the same target with source 4 excluded is fine
+        E, B = ctx.fields_at(T[-1], x, np.array([4]))
+        assert np.all(np.isfinite(E))
