@@ -1,0 +1,176 @@
+"""Throughput of the EM-PP Lienard-Wiechert hot path on one MI355X.
+
+A step is one pass of the whole hot path over the bunch: the all-pairs
+retarded-time search + LW field sum (pair kernel) and the Higuera-Cary
+push with the history update (push kernel).  Inputs are resident in HBM
+before the timed region.  Prints ONE JSON line on stdout; progress goes to
+stderr.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c3] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2605_05543_amd import bunch  # noqa: E402
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP64 operations of one (target, source) pair, counted from the
+# method's steps (add, sub, mul = 1; sqrt, div = 1; compare = 0):
+#   sign test of one stored sample (Sec. 2.2):      9 per probe
+#   root of Eq. (dt) incl. coefficients:           32
+#   reconstruction Eq. (linear) / (linear2):       20 / 6
+#   LW E and B, Eqs. (LW_E), (LW_B):               69 / 48 (a = 0 out of history)
+#   accumulation of E and B:                        6
+FLOP_PROBE = 9
+FLOP_INRING = 32 + 20 + 69 + 6
+FLOP_BEFORE = 32 + 6 + 48 + 6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_flops(counters):
+    return (FLOP_PROBE * counters["probes"] + FLOP_INRING * (counters["pairs"] - counters["before"])
+            + FLOP_BEFORE * counters["before"])
+
+
+def run_path(wl, r, u, precision, guess, steps, warmup):
+    import torch
+
+    from paper_2605_05543_amd._lib import Context
+
+    n = wl.bunch.n
+    ctx = Context(n=n, depth=wl.depth, q=-bunch.E_CHARGE, m=bunch.M_ELECTRON, dt=wl.dt, ext_field=wl.ext_field,
+                  dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re, precision=precision, guess=guess)
+    ctx.init_bunch(r, u, 0.0)
+    ctx.init_history_straight()
+    # one counting step (untimed) for the algorithmic work per launch
+    ctx.set_counting(True)
+    ctx.step(1)
+    cnt = ctx.counters()
+    ctx.set_counting(False)
+    if warmup:
+        ctx.step(warmup)
+    ctx.sync()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tim = ctx.timing()
+    ctx.set_timing(False)
+    d = ctx.diag()
+    ctx.close()
+    pairs = n * (n - 1)
+    pair_ms = tim["pair_ms"] / max(1, tim["pair_launches"])
+    flops = algorithmic_flops(cnt)
+    out = {
+        "precision": ["fp64", "mixed"][precision], "guess": ["bisect", "mlp", "ballistic"][guess],
+        "pair_evals_per_s": pairs * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+        "pair_kernel_ms": pair_ms, "push_kernel_ms": tim["push_ms"] / max(1, tim["push_launches"]),
+        "probes_per_pair": cnt["probes"] / cnt["pairs"], "before_history_fraction": cnt["before"] / cnt["pairs"],
+        "fallbacks": cnt["fallbacks"], "flops_per_pair": flops / cnt["pairs"],
+        "achieved_tflops": flops / (pair_ms * 1e-3) / 1e12, "sigma_after": d["sigma"],
+    }
+    log(f"  {out['precision']}/{out['guess']}: {out['pair_evals_per_s']:.3e} pair-evals/s, "
+        f"{out['ms_per_step']:.2f} ms/step, pair kernel {pair_ms:.2f} ms, {out['probes_per_pair']:.2f} probes/pair, "
+        f"{out['achieved_tflops']:.1f} TFLOP/s algorithmic")
+    return out
+
+
+def cpu_baseline(wl, r, u, target_seconds=15.0):
+    import oracle
+
+    orc = oracle.get()
+    n = wl.bunch.n
+    T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
+    threads = orc.max_threads()
+    probe = bunch.target_subset(n, 8, 1001)
+    t0 = time.perf_counter()
+    orc.fields(T, w, v, -bunch.E_CHARGE, T[-1], r[:, probe], probe)
+    rate = len(probe) / (time.perf_counter() - t0)
+    m = int(max(8, min(n, rate * target_seconds)))
+    sub = bunch.target_subset(n, m, 1002)
+    t0 = time.perf_counter()
+    orc.fields(T, w, v, -bunch.E_CHARGE, T[-1], r[:, sub], sub)
+    el = time.perf_counter() - t0
+    value = m * (n - 1) / el
+    log(f"  cpu oracle: {m} targets x {n - 1} sources in {el:.1f} s on {threads} threads: {value:.3e} pair-evals/s")
+    return {"value": value, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"fields at {m} seeded targets x {n - 1} sources, one step of {wl.name} "
+                      f"(FP64 C oracle, linear history scan), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--paths", default="fp64:bisect,fp64:ballistic")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the pair sum would shard by "
+              "targets with a replicated history; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    wl = {"c1": bunch.C1, "c2": bunch.C2, "c3": bunch.C3, "c5": bunch.C5}[args.workload]
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    log(f"workload {wl.name}: N={wl.bunch.n} D={wl.depth} dt={wl.dt} steps={args.steps} warmup={args.warmup}")
+    pmap = {"fp64": 0, "mixed": 1}
+    gmap = {"bisect": 0, "mlp": 1, "ballistic": 2}
+    results = []
+    for spec in args.paths.split(","):
+        p, g = spec.split(":")
+        results.append(run_path(wl, r, u, pmap[p], gmap[g], args.steps, args.warmup))
+    plain = results[0]
+    head = results[-1] if len(results) > 1 and results[-1]["precision"] == "mixed" else plain
+    n = wl.bunch.n
+    launch_flops = plain["flops_per_pair"] * n * (n - 1)
+    achieved = launch_flops / (plain["pair_kernel_ms"] * 1e-3) / 1e12
+    line = {
+        "metric": "LW pair-evals/s at N=65536 (FP32+surrogate vs FP64 plain, <=1e-5 rel err)",
+        "value": head["pair_evals_per_s"],
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head["precision"] == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": n, "depth": wl.depth, "dt": wl.dt, "ext_field": wl.ext_field,
+                   "precision": head["precision"], "search": head["guess"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": "pair_fp64_kernel (plain FP64 path)",
+                     "flops_per_pair": plain["flops_per_pair"], "launch_ms": plain["pair_kernel_ms"]},
+        "paths": results,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl, r, u)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

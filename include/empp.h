@@ -80,7 +80,7 @@ typedef enum {
 
 typedef struct {
     int64_t n;             /* particles, >= 2                                */
-    int32_t depth;         /* history slots D, 2 <= D <= 65536               */
+    int32_t depth;         /* history slots D, 2 <= D <= 4096                */
     int32_t ext_field;     /* 0: none; 1: centred dipole, moment along +z    */
     double q;              /* charge of every macro-particle (C)             */
     double m;              /* mass of every macro-particle (kg), > 0         */
@@ -179,6 +179,19 @@ empp_status empp_get_diag(empp_ctx *ctx, empp_diag *out);
  * only while counting is enabled).                                       */
 empp_status empp_set_counting(empp_ctx *ctx, int32_t enable);
 empp_status empp_get_counters(empp_ctx *ctx, empp_counters *out);
+
+typedef struct {
+    double pair_ms;        /* summed duration of pair-kernel launches (ms)   */
+    int64_t pair_launches;
+    double push_ms;        /* summed duration of push-kernel launches (ms)   */
+    int64_t push_launches;
+} empp_timing;
+
+/* Kernel timing with HIP events recorded on the context's stream around
+ * every pair and push launch while enabled.  empp_get_timing synchronises,
+ * returns the sums since the last call (or enable) and resets them.      */
+empp_status empp_set_timing(empp_ctx *ctx, int32_t enable);
+empp_status empp_get_timing(empp_ctx *ctx, empp_timing *out);
 
 /* Wait for the context's stream and report latched device errors.        */
 empp_status empp_sync(empp_ctx *ctx);

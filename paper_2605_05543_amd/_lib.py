@@ -25,7 +25,7 @@ EXPORTS = [
     "empp_workspace_size", "empp_create", "empp_destroy", "empp_last_error", "empp_init_bunch",
     "empp_init_history_straight", "empp_set_history", "empp_step", "empp_fields_at", "empp_fields_at_dev",
     "empp_get_state", "empp_get_history", "empp_get_fields", "empp_get_diag", "empp_set_counting",
-    "empp_get_counters", "empp_sync", "empp_set_mode",
+    "empp_get_counters", "empp_sync", "empp_set_mode", "empp_set_timing", "empp_get_timing",
 ]
 
 
@@ -57,6 +57,11 @@ class Counters(ctypes.Structure):
                 ("rescues", ctypes.c_uint64), ("fallbacks", ctypes.c_uint64)]
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("pair_ms", ctypes.c_double), ("pair_launches", ctypes.c_int64), ("push_ms", ctypes.c_double),
+                ("push_launches", ctypes.c_int64)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I32 = ctypes.c_int32
@@ -84,6 +89,8 @@ def _load():
         "empp_get_counters": [_P, ctypes.POINTER(Counters)],
         "empp_sync": [_P],
         "empp_set_mode": [_P, _I32, _I32],
+        "empp_set_timing": [_P, _I32],
+        "empp_get_timing": [_P, ctypes.POINTER(Timing)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -204,6 +211,17 @@ def empp_get_counters(h):
             "fallbacks": c.fallbacks}
 
 
+def empp_set_timing(h, enable=True):
+    _check(lib.empp_set_timing(h, 1 if enable else 0))
+
+
+def empp_get_timing(h):
+    t = Timing()
+    _check(lib.empp_get_timing(h, ctypes.byref(t)))
+    return {"pair_ms": t.pair_ms, "pair_launches": t.pair_launches, "push_ms": t.push_ms,
+            "push_launches": t.push_launches}
+
+
 def empp_sync(h):
     _check(lib.empp_sync(h))
 
@@ -293,6 +311,12 @@ class Context:
 
     def sync(self):
         empp_sync(self.h)
+
+    def set_timing(self, enable=True):
+        empp_set_timing(self.h, enable)
+
+    def timing(self):
+        return empp_get_timing(self.h)
 
     def set_mode(self, precision, guess):
         empp_set_mode(self.h, precision, guess)

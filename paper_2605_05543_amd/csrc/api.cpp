@@ -15,14 +15,15 @@
 #include "empp_dev.h"
 
 namespace empp {
+int pair_fp64_tile(int D);
 hipError_t launch_pair_fp64(const PairParams &p, hipStream_t stream, bool kstar, bool count);
 hipError_t launch_pair_mixed(const PairParams &p, hipStream_t stream, bool kstar, bool count);
 hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, double *E, double *B, hipStream_t s);
 hipError_t launch_push(const PushParams &p, hipStream_t s);
 hipError_t launch_init_straight(double4 *rw, double4 *rv, double *T, const double *r, const double *u, int64_t N,
                                 int D, double t0, double dt, hipStream_t s);
-hipError_t launch_history_to_ring(const double *w, const double *v, double4 *rw, double4 *rv, int64_t N, int D,
-                                  hipStream_t s);
+hipError_t launch_history_to_ring(const double *w, const double *v, const double *T, double4 *rw, double4 *rv,
+                                  int64_t N, int D, hipStream_t s);
 hipError_t launch_ring_to_history(const double4 *rw, const double4 *rv, double *w, double *v, int64_t N, int D,
                                   int head, hipStream_t s);
 hipError_t launch_newest_positions(const double4 *rw, double *r, int64_t N, int D, int head, hipStream_t s);
@@ -62,10 +63,59 @@ constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, total;
+    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, order, total;
 };
 
-int tile_for_depth(int D) { return std::max(1, 2048 / D); }
+int tile_for_depth(int D) { return pair_fp64_tile(D); }
+
+int bisection_steps(int D)
+{
+    int nit = 0;
+    while ((1 << nit) < D - 1)
+        ++nit;
+    return nit;
+}
+
+// Spatial (Morton, 21 bits per axis) order of points x[3][N]: the pair
+// kernels visit targets in this order so that the lanes of a wavefront are
+// neighbours and probe nearby history slots.  Only the mapping of targets
+// to threads changes; every target's sum is unaffected.
+std::vector<int32_t> morton_order(const double *x, int64_t N)
+{
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) {
+        lo[c] = hi[c] = x[c * N];
+        for (int64_t i = 1; i < N; ++i) {
+            lo[c] = std::min(lo[c], x[c * N + i]);
+            hi[c] = std::max(hi[c], x[c * N + i]);
+        }
+    }
+    auto spread = [](uint64_t v) {
+        v &= 0x1fffff;
+        v = (v | v << 32) & 0x1f00000000ffffull;
+        v = (v | v << 16) & 0x1f0000ff0000ffull;
+        v = (v | v << 8) & 0x100f00f00f00f00full;
+        v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+        v = (v | v << 2) & 0x1249249249249249ull;
+        return v;
+    };
+    std::vector<std::pair<uint64_t, int32_t>> key(N);
+    for (int64_t i = 0; i < N; ++i) {
+        uint64_t code = 0;
+        for (int c = 0; c < 3; ++c) {
+            double span = hi[c] - lo[c];
+            double f = span > 0 ? (x[c * N + i] - lo[c]) / span : 0.0;
+            uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, f * 2097151.0));
+            code |= spread(q) << c;
+        }
+        key[i] = {code, (int32_t)i};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> order(N);
+    for (int64_t i = 0; i < N; ++i)
+        order[i] = key[i].second;
+    return order;
+}
 
 int splits_for(const empp_config &c)
 {
@@ -99,6 +149,7 @@ Layout layout_for(const empp_config &c)
     L.err = take(2 * sizeof(unsigned long long));
     L.counters = take(8 * sizeof(unsigned long long));
     L.diag = take(((N + kBlock - 1) / kBlock) * 7 * sizeof(double));
+    L.order = take(N * sizeof(int32_t));
     L.total = o;
     return L;
 }
@@ -158,6 +209,11 @@ struct empp_ctx {
     double t_origin = 0.0;  // T of step 0
     double t_now = 0.0;
     std::vector<double> r0, u0;  // bunch before the history is built
+    // kernel timing (HIP events on the context's stream)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<size_t, int>> ev_marks;  // (start index, kind 0 pair / 1 push)
 
     template <typename Tp>
     Tp *at(uint64_t off) const { return reinterpret_cast<Tp *>(ws + off); }
@@ -171,6 +227,7 @@ struct empp_ctx {
     unsigned long long *err() const { return at<unsigned long long>(L.err); }
     unsigned long long *counters() const { return at<unsigned long long>(L.counters); }
     double *diag() const { return at<double>(L.diag); }
+    int32_t *order() const { return at<int32_t>(L.order); }
 };
 
 namespace {
@@ -221,6 +278,8 @@ PairParams pair_params(empp_ctx *ctx)
     p.nsplit = ctx->nsplit;
     p.src_per_split = (ctx->cfg.n + ctx->nsplit - 1) / ctx->nsplit;
     p.tile = ctx->tile;
+    p.nit = bisection_steps(ctx->cfg.depth);
+    p.order = nullptr;
     p.part = ctx->part();
     p.err = ctx->err();
     p.counters = ctx->counters();
@@ -229,11 +288,45 @@ PairParams pair_params(empp_ctx *ctx)
     return p;
 }
 
+// Record an event on the context's stream (timing mode only).  Events are
+// created once and reused; a failure just disables timing.
+hipError_t timing_event(empp_ctx *ctx)
+{
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess)
+            return err;
+        ctx->ev_pool.push_back(e);
+    }
+    return hipEventRecord(ctx->ev_pool[ctx->ev_used++], ctx->stream);
+}
+
+template <typename F>
+hipError_t timed(empp_ctx *ctx, int kind, F &&launch)
+{
+    if (!ctx->timing)
+        return launch();
+    size_t at = ctx->ev_used;
+    hipError_t e = timing_event(ctx);
+    if (e != hipSuccess)
+        return e;
+    e = launch();
+    if (e != hipSuccess)
+        return e;
+    e = timing_event(ctx);
+    if (e == hipSuccess)
+        ctx->ev_marks.push_back({at, kind});
+    return e;
+}
+
 hipError_t launch_pair(empp_ctx *ctx, const PairParams &p, bool kstar)
 {
-    if (ctx->cfg.precision == EMPP_MIXED)
-        return launch_pair_mixed(p, ctx->stream, kstar, ctx->counting);
-    return launch_pair_fp64(p, ctx->stream, kstar, ctx->counting);
+    return timed(ctx, 0, [&]() {
+        if (ctx->cfg.precision == EMPP_MIXED)
+            return launch_pair_mixed(p, ctx->stream, kstar, ctx->counting);
+        return launch_pair_fp64(p, ctx->stream, kstar, ctx->counting);
+    });
 }
 
 }  // namespace
@@ -314,6 +407,8 @@ void empp_destroy(empp_ctx *ctx)
         return;
     (void)hipSetDevice(ctx->cfg.device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t e : ctx->ev_pool)
+        (void)hipEventDestroy(e);
     if (ctx->owns_ws && ctx->ws)
         (void)hipFree(ctx->ws);
     delete ctx;
@@ -352,6 +447,8 @@ empp_status empp_init_history_straight(empp_ctx *ctx)
     HIP_TRY(hipMemcpyAsync(ctx->u(), ctx->u0.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(launch_init_straight(ctx->ring_w(), ctx->ring_v(), ctx->T(), r_dev, ctx->u(), N, D, ctx->t_origin,
                                  ctx->cfg.dt, ctx->stream));
+    std::vector<int32_t> ord = morton_order(ctx->r0.data(), N);
+    HIP_TRY(hipMemcpyAsync(ctx->order(), ord.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipMemsetAsync(ctx->E(), 0, 3 * N * sizeof(double), ctx->stream));
     HIP_TRY(hipMemsetAsync(ctx->B(), 0, 3 * N * sizeof(double), ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -396,9 +493,12 @@ empp_status empp_set_history(empp_ctx *ctx, int32_t nslots, const double *T, con
     auto body = [&]() -> empp_status {
         HIP_TRY(hipMemcpyAsync(tmp, w, tot * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
         HIP_TRY(hipMemcpyAsync(tmp + tot, v, tot * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-        HIP_TRY(launch_history_to_ring(tmp, tmp + tot, ctx->ring_w(), ctx->ring_v(), N, D, ctx->stream));
         HIP_TRY(hipMemcpyAsync(ctx->T(), T, D * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(launch_history_to_ring(tmp, tmp + tot, ctx->T(), ctx->ring_w(), ctx->ring_v(), N, D, ctx->stream));
         HIP_TRY(hipMemcpyAsync(ctx->u(), u, 3 * N * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        std::vector<int32_t> ord = morton_order(w + (uint64_t)(D - 1) * 3 * N, N);
+        HIP_TRY(hipMemcpyAsync(ctx->order(), ord.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
         HIP_TRY(hipMemsetAsync(ctx->E(), 0, 3 * N * sizeof(double), ctx->stream));
         HIP_TRY(hipMemsetAsync(ctx->B(), 0, 3 * N * sizeof(double), ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -438,6 +538,7 @@ empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
         PairParams p = pair_params(ctx);
         p.x = nullptr;
         p.self_index = nullptr;
+        p.order = ctx->order();
         p.m = N;
         p.kstar = nullptr;
         HIP_TRY(launch_pair(ctx, p, false));
@@ -454,12 +555,13 @@ empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
         q.D = ctx->cfg.depth;
         q.head = ctx->head;
         q.dt = ctx->cfg.dt;
+        q.t_now = ctx->t_now;
         q.t_next = ctx->t_origin + (double)(ctx->step + 1) * ctx->cfg.dt;
         q.eps = ctx->cfg.q * ctx->cfg.dt / (2.0 * ctx->cfg.m);
         q.ext_field = ctx->cfg.ext_field;
         q.dip_k = ctx->cfg.dipole_b0 * ctx->cfg.dipole_re * ctx->cfg.dipole_re * ctx->cfg.dipole_re;
         q.self_field = 1;
-        HIP_TRY(launch_push(q, ctx->stream));
+        HIP_TRY(timed(ctx, 1, [&]() { return launch_push(q, ctx->stream); }));
         ctx->head = ctx->head + 1 == ctx->cfg.depth ? 0 : ctx->head + 1;
         ctx->step += 1;
         ctx->t_now = q.t_next;
@@ -759,6 +861,45 @@ empp_status empp_get_counters(empp_ctx *ctx, empp_counters *out)
     out->probes = h[2];
     out->rescues = h[3];
     out->fallbacks = h[4];
+    return EMPP_OK;
+}
+
+empp_status empp_set_timing(empp_ctx *ctx, int32_t enable)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->timing = enable != 0;
+    ctx->ev_used = 0;
+    ctx->ev_marks.clear();
+    return EMPP_OK;
+}
+
+empp_status empp_get_timing(empp_ctx *ctx, empp_timing *out)
+{
+    if (!ctx || !out)
+        return fail(EMPP_EINVAL, "NULL argument");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    *out = empp_timing{};
+    for (auto &mk : ctx->ev_marks) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev_pool[mk.first], ctx->ev_pool[mk.first + 1]));
+        if (mk.second == 0) {
+            out->pair_ms += ms;
+            out->pair_launches += 1;
+        } else {
+            out->push_ms += ms;
+            out->push_launches += 1;
+        }
+    }
+    ctx->ev_used = 0;
+    ctx->ev_marks.clear();
     return EMPP_OK;
 }
 

@@ -16,7 +16,7 @@ constexpr int kMaxSplits = 1024;   // source chunks of one launch
 
 // History layout in HBM (library-owned workspace):
 //   ring_w[j * D + p] = {x, y, z, 0}     position of source j at physical slot p
-//   ring_v[j * D + p] = {vx, vy, vz, 0}  velocity leaving that slot
+//   ring_v[j * D + p] = {vx, vy, vz, T}  velocity leaving that slot, slot time
 //   T[p]                                  slot time
 // Slot p holds logical slot "back" b (0 = newest) when p = (head - b) mod D.
 // A source's whole history is one contiguous 32*D-byte block, so a block
@@ -36,6 +36,8 @@ struct PairParams {
     // pair (a, a) is skipped).
     const double *x;
     const int64_t *self_index;  // external mode only, may be null
+    const int32_t *order;       // step mode: target slot -> particle (spatial order), may be null
+    int32_t nit;                // bisection steps: ceil(log2(D - 1))
     int64_t m;
     int64_t src_per_split;
     int32_t nsplit;
@@ -65,6 +67,7 @@ struct PushParams {
     int32_t D;
     int32_t head;       // newest physical slot before the push
     double dt;
+    double t_now;       // time of the newest slot before the push
     double t_next;      // time of the new slot
     double eps;         // q dt / (2 m)
     int32_t ext_field;

@@ -2,15 +2,19 @@
 // precision (Secs. 2.1-2.2 of arXiv 2605.05543).
 //
 // One thread owns one target.  A block of 256 targets walks its chunk of
-// sources in tiles: the tile's histories (positions plus the light
-// distance c (t - T_k) of every slot) are staged once into LDS and every
-// target of the block then searches them, so each history byte read from
-// HBM serves 256 targets.  The bracket velocities v_1, v_2 are read from
-// the (L2-resident) history in HBM after the search.  Sums are kept per
-// target in registers: a plain partial sum per tile, merged into a
-// Neumaier-compensated total after each tile; source chunks (grid.y) write
-// (sum, compensation) partials that the push kernel merges in a fixed
-// order, so results do not depend on scheduling.
+// sources in tiles of S sources: the tile's histories (positions plus the
+// light distance c (t - T_k) of every slot) are staged once into LDS and
+// every target of the block then searches them, so each history byte read
+// from L2/HBM serves 256 targets.  The S searches of a tile run in
+// lockstep (a fixed number of bisection steps, no divergence), so S
+// independent LDS chains are in flight per lane; then the 2 S bracket
+// velocity records are fetched together and the S pair fields evaluated.
+// Targets are visited in a spatial (Morton) order so that the lanes of a
+// wavefront probe nearby history slots.  Sums are kept per target in
+// registers: a plain partial per tile merged into a Neumaier-compensated
+// total; source chunks (grid.y) write (sum, compensation) partials that the
+// push kernel merges in a fixed order, so results do not depend on
+// scheduling.
 #include "pair_common.h"
 
 namespace empp {
@@ -24,11 +28,11 @@ struct LdsRec {
 
 // Retarded root, reconstruction and LW field of one pair (Eqs. dt,
 // linear, linear2, LW_E, LW_B).  w1 = {x, y, z, L1} is the bracket's older
-// sample with L1 = c (t - t_1); v1, v2 the velocities of the bracket ends;
-// inv_h = 1/(t_2 - t_1).  Adds E and B into acc[0..5].  Returns false on a
-// numerical failure (negative discriminant or eta = 0).
-__device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, double4 v1, double4 v2,
-                               double inv_h, bool before, double kq, double acc[6])
+// sample with L1 = c (t - t_1); v1, v2 = {v, T} the velocity records of the
+// bracket ends.  Writes E and B into f[0..5].  Returns false on a numerical
+// failure (negative discriminant or eta <= 0).
+__device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, double4 v1, double4 v2, bool before,
+                               double kq, double f[6])
 {
     const double c = kC_LIGHT;
     const double c2 = c * c;
@@ -44,21 +48,11 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
     double sq = sqrt(fmax(disc, 0.0));
     double dtr = 2.0 * C0 * rcp64(sq - C1);
     // reconstruction: w = w1 + v1 dt; v = v1 + (v2 - v1) df; a = (v2 - v1)/h
-    double ax = 0.0, ay = 0.0, az = 0.0, df = 0.0;
-    if (!before) {
-        ax = (v2.x - v1.x) * inv_h;
-        ay = (v2.y - v1.y) * inv_h;
-        az = (v2.z - v1.z) * inv_h;
-        df = dtr * inv_h;
-    }
-    double vrx = v1.x + (v2.x - v1.x) * df;
-    double vry = v1.y + (v2.y - v1.y) * df;
-    double vrz = v1.z + (v2.z - v1.z) * df;
-    if (before) {
-        vrx = v1.x;
-        vry = v1.y;
-        vrz = v1.z;
-    }
+    double inv_h = before ? 0.0 : rcp64(v2.w - v1.w);
+    double gx = v2.x - v1.x, gy = v2.y - v1.y, gz = v2.z - v1.z;
+    double ax = gx * inv_h, ay = gy * inv_h, az = gz * inv_h;  // zero out of history
+    double df = dtr * inv_h;
+    double vrx = v1.x + gx * df, vry = v1.y + gy * df, vrz = v1.z + gz * df;
     double ex = dx - v1.x * dtr, ey = dy - v1.y * dtr, ez = dz - v1.z * dtr;  // eta
     // |eta| = c (t - t_r) on the reconstructed segment
     double en = L1 - c * dtr;
@@ -78,23 +72,18 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
     double Ey = pref * (cv * py + rdy);
     double Ez = pref * (cv * pz + rdz);
     const double ic = 1.0 / c;
-    double Bx = (hy * Ez - hz * Ey) * ic;
-    double By = (hz * Ex - hx * Ez) * ic;
-    double Bz = (hx * Ey - hy * Ex) * ic;
-    if (ok) {
-        acc[0] += Ex;
-        acc[1] += Ey;
-        acc[2] += Ez;
-        acc[3] += Bx;
-        acc[4] += By;
-        acc[5] += Bz;
-    }
+    f[0] = Ex;
+    f[1] = Ey;
+    f[2] = Ez;
+    f[3] = (hy * Ez - hz * Ey) * ic;
+    f[4] = (hz * Ex - hx * Ez) * ic;
+    f[5] = (hx * Ey - hy * Ex) * ic;
     return ok;
 }
 
 }  // namespace
 
-template <bool KSTAR, bool COUNT, int GUESS>
+template <bool KSTAR, bool COUNT, int GUESS, int S>
 __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
 {
     extern __shared__ double4 lds[];
@@ -109,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
         j1 = p.n_src;
 
     double rx = 0, ry = 0, rz = 0;
-    int64_t self = -1;
+    int64_t self = -1, tgt = a;  // tgt: index the outputs are written at
     if (active) {
         if (p.x) {
             rx = p.x[a];
@@ -117,11 +106,12 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
             rz = p.x[2 * p.m + a];
             self = p.self_index ? p.self_index[a] : -1;
         } else {
-            double4 w = p.ring_w[a * D + p.head];
+            tgt = p.order ? (int64_t)p.order[a] : a;
+            double4 w = p.ring_w[tgt * D + p.head];
             rx = w.x;
             ry = w.y;
             rz = w.z;
-            self = a;
+            self = tgt;
         }
     }
     double sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
@@ -130,8 +120,8 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
     int64_t fail_j = 0;
     const float inv_cdt = (float)(1.0 / (kC_LIGHT * p.dt));
 
-    for (int64_t jt = j0; jt < j1; jt += p.tile) {
-        const int ns = (int)((j1 - jt) < p.tile ? (j1 - jt) : p.tile);
+    for (int64_t jt = j0; jt < j1; jt += S) {
+        const int ns = (int)((j1 - jt) < S ? (j1 - jt) : S);
         __syncthreads();
         for (int s = 0; s < ns; ++s) {
             const double4 *src = p.ring_w + (jt + s) * D;
@@ -146,101 +136,171 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
         __syncthreads();
         if (!active)
             continue;
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        for (int s = 0; s < ns; ++s) {
-            const int64_t j = jt + s;
-            if (j == self) {
-                if (KSTAR)
-                    p.kstar[a * p.n_src + j] = 0;
-                continue;
+
+        bool valid[S];
+        int64_t jj[S];
+        int bk[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            jj[s] = jt + (s < ns ? s : 0);
+            valid[s] = s < ns && jj[s] != self;
+            if (KSTAR && s < ns && jj[s] == self)
+                p.kstar[a * p.n_src + jj[s]] = 0;
+            // a target on the source's present position: eta = 0
+            double4 wn = lds[s * D];
+            if (valid[s] && rx == wn.x && ry == wn.y && rz == wn.z) {
+                if (!failed)
+                    fail_j = jj[s];
+                failed = true;
+                valid[s] = false;
             }
-            LdsRec rec{lds + s * D};
-            {
-                // a target on the source's present position: eta = 0
-                double4 wn = rec(0);
-                if (rx == wn.x && ry == wn.y && rz == wn.z) {
-                    if (!failed)
-                        fail_j = j;
-                    failed = true;
-                    continue;
+        }
+
+        if (GUESS == 0) {
+            // The paper's search: oldest sample first, then bisection of the
+            // whole history; a fixed number of halvings keeps the S searches
+            // in lockstep (extra halvings of a one-step bracket change
+            // nothing).
+            bool inside[S];
+            int lo[S], hi[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                inside[s] = lightcone_positive(lds[s * D + D - 1], rx, ry, rz);
+                lo[s] = D - 1;
+                hi[s] = 0;
+            }
+            bool any = false;
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                any = any || (inside[s] && valid[s]);
+            if (__any(any)) {
+                for (int it = 0; it < p.nit; ++it) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        int mid = (lo[s] + hi[s]) >> 1;
+                        bool f = lightcone_positive(lds[s * D + mid], rx, ry, rz);
+                        lo[s] = f ? mid : lo[s];
+                        hi[s] = f ? hi[s] : mid;
+                    }
                 }
             }
-            int b;
-            if (GUESS == 0) {
-                b = search_bisect(rec, D, rx, ry, rz, probes);
-            } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                bk[s] = inside[s] ? lo[s] : -1;
+                if (COUNT && valid[s])
+                    probes += inside[s] ? 1 + p.nit : 1;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                bk[s] = -1;
+                if (!valid[s])
+                    continue;
+                LdsRec rec{lds + s * D};
                 double4 wn = rec(0);
-                double4 vn = p.ring_v[j * D + p.head];
+                double4 vn = p.ring_v[jj[s] * D + p.head];
                 float g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
                 int fb = 0;
-                b = search_guided(rec, D, rx, ry, rz, g, 6, probes, fb);
+                bk[s] = search_guided(rec, D, rx, ry, rz, g, 6, probes, fb);
                 nfall += fb;
             }
-            const bool before = b < 0;
-            const int bb = before ? D - 1 : b;
+        }
+
+        // bracket velocity records (they carry their slot times)
+        double4 v1[S], v2[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bool before = bk[s] < 0;
+            const int bb = before ? D - 1 : bk[s];
             int ph1 = p.head - bb;
             ph1 += ph1 < 0 ? D : 0;
             int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
-            double4 w1 = rec(bb);
-            double4 v1 = p.ring_v[j * D + ph1];
-            double4 v2 = before ? v1 : p.ring_v[j * D + ph2];
-            double inv_h = before ? 0.0 : rcp64(p.T[ph2] - p.T[ph1]);
-            if (!lw_pair(rx, ry, rz, w1, v1, v2, inv_h, before, p.kq, acc)) {
-                if (!failed)
-                    fail_j = j;
-                failed = true;
-            }
-            if (KSTAR)
-                p.kstar[a * p.n_src + j] = before ? -1 : b;
-            if (COUNT) {
-                npairs += 1;
-                nbefore += before ? 1 : 0;
+            v1[s] = p.ring_v[jj[s] * D + ph1];
+            v2[s] = before ? v1[s] : p.ring_v[jj[s] * D + ph2];
+        }
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bool before = bk[s] < 0;
+            const int bb = before ? D - 1 : bk[s];
+            double f[6];
+            bool ok = lw_pair(rx, ry, rz, lds[s * D + bb], v1[s], v2[s], before, p.kq, f);
+            if (valid[s]) {
+                if (ok) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        acc[k] += f[k];
+                } else {
+                    if (!failed)
+                        fail_j = jj[s];
+                    failed = true;
+                }
+                if (KSTAR)
+                    p.kstar[a * p.n_src + jj[s]] = before ? -1 : bk[s];
+                if (COUNT) {
+                    npairs += 1;
+                    nbefore += before ? 1 : 0;
+                }
             }
         }
+#pragma unroll
         for (int k = 0; k < 6; ++k)
             neumaier(sum[k], comp[k], acc[k]);
     }
     if (active) {
-        double *out = p.part + (int64_t)split * 12 * p.m + a;
+        double *out = p.part + (int64_t)split * 12 * p.m + tgt;
         for (int k = 0; k < 6; ++k) {
             out[k * p.m] = sum[k];
             out[(6 + k) * p.m] = comp[k];
         }
         if (failed)
-            report_error(p.err, a, fail_j, kErrCoincident);
+            report_error(p.err, tgt, fail_j, kErrCoincident);
     }
     if (COUNT) {
         // one atomic per wavefront
-        unsigned long long v0 = npairs, v1 = nbefore, v2 = probes, v3 = nfall;
+        unsigned long long c0 = npairs, c1 = nbefore, c2 = probes, c3 = nfall;
         for (int off = 32; off > 0; off >>= 1) {
-            v0 += __shfl_down(v0, off);
-            v1 += __shfl_down(v1, off);
-            v2 += __shfl_down(v2, off);
-            v3 += __shfl_down(v3, off);
+            c0 += __shfl_down(c0, off);
+            c1 += __shfl_down(c1, off);
+            c2 += __shfl_down(c2, off);
+            c3 += __shfl_down(c3, off);
         }
         if ((tid & 63) == 0) {
-            atomicAdd(&p.counters[0], v0);
-            atomicAdd(&p.counters[1], v1);
-            atomicAdd(&p.counters[2], v2);
-            atomicAdd(&p.counters[4], v3);
+            atomicAdd(&p.counters[0], c0);
+            atomicAdd(&p.counters[1], c1);
+            atomicAdd(&p.counters[2], c2);
+            atomicAdd(&p.counters[4], c3);
         }
     }
 }
+
+// Sources per LDS tile for a history depth: two when two histories fit in
+// 64 KiB, else one (depths up to 4096 use up to 128 KiB).
+int pair_fp64_tile(int D) { return D <= 1024 ? 2 : 1; }
 
 // Host-side launcher (called from the C ABI layer).
 hipError_t launch_pair_fp64(const PairParams &p, hipStream_t stream, bool kstar, bool count)
 {
     dim3 grid((unsigned)((p.m + kBlock - 1) / kBlock), (unsigned)p.nsplit);
     size_t lds = (size_t)p.tile * p.D * sizeof(double4);
-#define EMPP_LAUNCH(K, C, G) \
-    hipLaunchKernelGGL((pair_fp64_kernel<K, C, G>), grid, dim3(kBlock), lds, stream, p)
-    if (p.guess == 2) {
-        if (kstar) { if (count) EMPP_LAUNCH(true, true, 2); else EMPP_LAUNCH(true, false, 2); }
-        else { if (count) EMPP_LAUNCH(false, true, 2); else EMPP_LAUNCH(false, false, 2); }
+#define EMPP_LAUNCH(K, C, G, S)                                                                              \
+    do {                                                                                                    \
+        if (lds > 65536)                                                                                    \
+            (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, C, G, S>,                           \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+        hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S>), grid, dim3(kBlock), lds, stream, p);             \
+    } while (0)
+#define EMPP_BY_TILE(K, C, G) \
+    do { if (p.tile == 2) EMPP_LAUNCH(K, C, G, 2); else EMPP_LAUNCH(K, C, G, 1); } while (0)
+#define EMPP_BY_GUESS(K, C) \
+    do { if (p.guess == 2) EMPP_BY_TILE(K, C, 2); else EMPP_BY_TILE(K, C, 0); } while (0)
+    if (kstar) {
+        if (count) EMPP_BY_GUESS(true, true); else EMPP_BY_GUESS(true, false);
     } else {
-        if (kstar) { if (count) EMPP_LAUNCH(true, true, 0); else EMPP_LAUNCH(true, false, 0); }
-        else { if (count) EMPP_LAUNCH(false, true, 0); else EMPP_LAUNCH(false, false, 0); }
+        if (count) EMPP_BY_GUESS(false, true); else EMPP_BY_GUESS(false, false);
     }
+#undef EMPP_BY_GUESS
+#undef EMPP_BY_TILE
 #undef EMPP_LAUNCH
     return hipGetLastError();
 }

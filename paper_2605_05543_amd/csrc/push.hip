@@ -113,10 +113,12 @@ __global__ void push_kernel(PushParams p)
     const double c = kC_LIGHT;
     double g = sqrt(1.0 + (ux * ux + uy * uy + uz * uz) / (c * c));
     double ig = 1.0 / g;
-    double4 vn = make_double4(ux * ig, uy * ig, uz * ig, 0.0);
+    // velocity records carry their slot time in .w
+    double4 vn = make_double4(ux * ig, uy * ig, uz * ig, p.t_now);
     p.ring_v[i * D + p.head] = vn;
     int nh = p.head + 1 == D ? 0 : p.head + 1;
     p.ring_w[i * D + nh] = make_double4(y.x + vn.x * p.dt, y.y + vn.y * p.dt, y.z + vn.z * p.dt, 0.0);
+    vn.w = p.t_next;
     p.ring_v[i * D + nh] = vn;
     if (i == 0)
         p.T[nh] = p.t_next;
@@ -142,15 +144,15 @@ __global__ void init_straight_kernel(double4 *ring_w, double4 *ring_v, double *T
     int64_t k = (int64_t)s - (D - 1);
     double kdt = (double)k * dt;
     ring_w[idx] = make_double4(r[i] + vx * kdt, r[N + i] + vy * kdt, r[2 * N + i] + vz * kdt, 0.0);
-    ring_v[idx] = make_double4(vx, vy, vz, 0.0);
+    ring_v[idx] = make_double4(vx, vy, vz, t0 + kdt);
     if (i == 0)
         T[s] = t0 + kdt;
 }
 
 // [ns][3][N] component-major history (oldest first) -> ring layout with
 // logical slot s at physical slot s (head = D - 1).
-__global__ void history_to_ring_kernel(const double *w, const double *v, double4 *ring_w, double4 *ring_v,
-                                       int64_t N, int D)
+__global__ void history_to_ring_kernel(const double *w, const double *v, const double *T, double4 *ring_w,
+                                       double4 *ring_v, int64_t N, int D)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= N * D)
@@ -160,7 +162,7 @@ __global__ void history_to_ring_kernel(const double *w, const double *v, double4
     const double *ws = w + s * 3 * N;
     const double *vs = v + s * 3 * N;
     ring_w[idx] = make_double4(ws[i], ws[N + i], ws[2 * N + i], 0.0);
-    ring_v[idx] = make_double4(vs[i], vs[N + i], vs[2 * N + i], 0.0);
+    ring_v[idx] = make_double4(vs[i], vs[N + i], vs[2 * N + i], T[s]);
 }
 
 // Ring -> [D][3][N] oldest first (logical order).
@@ -255,12 +257,12 @@ hipError_t launch_init_straight(double4 *rw, double4 *rv, double *T, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_history_to_ring(const double *w, const double *v, double4 *rw, double4 *rv, int64_t N, int D,
-                                  hipStream_t s)
+hipError_t launch_history_to_ring(const double *w, const double *v, const double *T, double4 *rw, double4 *rv,
+                                  int64_t N, int D, hipStream_t s)
 {
     int64_t tot = N * D;
-    hipLaunchKernelGGL(history_to_ring_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, w, v, rw, rv,
-                       N, D);
+    hipLaunchKernelGGL(history_to_ring_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, w, v, T, rw,
+                       rv, N, D);
     return hipGetLastError();
 }
 
