@@ -69,6 +69,14 @@ _I64 = ctypes.c_int64
 
 
 def _load():
+    # PyTorch brings its own HIP runtime.  Importing it first makes
+    # libempp.so bind to that same runtime (same soname), so torch's streams
+    # and device pointers are valid in the library and only one runtime is
+    # loaded in the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
     L = ctypes.CDLL(LIB_PATH)

@@ -11,12 +11,16 @@ namespace empp {
 constexpr double kC_LIGHT = 299792458.0;
 constexpr double kMU0 = 1.25663706212e-6;
 
-constexpr int kBlock = 256;        // threads per block of the pair kernels
+#ifndef EMPP_PAIR_BLOCK
+#define EMPP_PAIR_BLOCK 512
+#endif
+constexpr int kBlock = EMPP_PAIR_BLOCK;  // threads per block of the pair kernels
 constexpr int kMaxSplits = 1024;   // source chunks of one launch
 
 // History layout in HBM (library-owned workspace):
 //   ring_w[j * D + p] = {x, y, z, 0}     position of source j at physical slot p
-//   ring_v[j * D + p] = {vx, vy, vz, T}  velocity leaving that slot, slot time
+//   ring_v[j * D + p] = {vx, vy, vz, 1/h} velocity leaving that slot and the
+//                                         inverse length of its segment (0: newest)
 //   T[p]                                  slot time
 // Slot p holds logical slot "back" b (0 = newest) when p = (head - b) mod D.
 // A source's whole history is one contiguous 32*D-byte block, so a block

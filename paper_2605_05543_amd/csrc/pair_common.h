@@ -7,8 +7,8 @@
 namespace empp {
 
 // Staged history record of one source at one logical slot:
-// {x, y, z, L} with L = c (t - T_k) the light distance back to the slot.
-// The sign test f_k > 0 <=> L*L > (dx*dx + dy*dy) + dz*dz is evaluated
+// {x, y, z, L2} with L2 = L*L, L = c (t - T_k) the light distance back to the
+// slot.  The sign test f_k > 0 <=> L*L > (dx*dx + dy*dy) + dz*dz is evaluated
 // without fused multiply-adds and in this association, so it rounds
 // exactly like a plain IEEE evaluation of the same expression.
 __device__ inline bool lightcone_positive(double4 rec, double rx, double ry, double rz)
@@ -17,8 +17,7 @@ __device__ inline bool lightcone_positive(double4 rec, double rx, double ry, dou
     double dx = rx - rec.x;
     double dy = ry - rec.y;
     double dz = rz - rec.z;
-    double L = rec.w;
-    return L * L > (dx * dx + dy * dy) + dz * dz;
+    return rec.w > (dx * dx + dy * dy) + dz * dz;
 }
 
 // Bisection of the paper: test the oldest sample first (if it is not
@@ -45,8 +44,9 @@ __device__ inline int search_bisect(Rec rec, int D, double rx, double ry, double
     return lo;
 }
 
-// Guided search: start at a guessed back offset g, confirm with the
-// neighbouring sample, otherwise gallop (1, 2, 4, ... slots) towards the
+// Guided search: start at a guessed back offset g and test g and g-1
+// together (both loads in flight at once); when the guess is right this is
+// the whole search.  Otherwise gallop (1, 2, 4, ... slots) towards the
 // bracket and bisect inside the last gallop step.  Reaches the same b* as
 // search_bisect for any guess.  A non-finite guess or more than
 // max_gallop doublings falls back to plain bisection of what is left
@@ -55,16 +55,20 @@ template <typename Rec>
 __device__ inline int search_guided(Rec rec, int D, double rx, double ry, double rz, float guess,
                                     int max_gallop, int &probes, int &fallback)
 {
-    int lo, hi;  // f(lo) > 0 (older side), f(hi) <= 0 (newer side)
     if (!(guess == guess) || !(fabsf(guess) < 1e9f)) {
         fallback = 1;
         return search_bisect(rec, D, rx, ry, rz, probes);
     }
     int g = (int)ceilf(guess);
     g = g < 1 ? 1 : (g > D - 1 ? D - 1 : g);
-    probes += 1;
-    if (lightcone_positive(rec(g), rx, ry, rz)) {
-        lo = g;
+    const bool fg = lightcone_positive(rec(g), rx, ry, rz);
+    const bool fg1 = g > 1 && lightcone_positive(rec(g - 1), rx, ry, rz);  // b = 0 is never inside
+    probes += g > 1 ? 2 : 1;
+    if (fg && !fg1)
+        return g;
+    int lo, hi;  // f(lo) > 0 (older side), f(hi) <= 0 (newer side)
+    if (fg) {
+        lo = g - 1;
         hi = 0;
         int step = 1, n = 0;
         while (true) {
@@ -93,6 +97,8 @@ __device__ inline int search_guided(Rec rec, int D, double rx, double ry, double
             if (cand >= D - 1 || n >= max_gallop) {
                 if (n >= max_gallop)
                     fallback = 1;
+                if (hi == D - 1)
+                    return -1;  // the oldest sample was the guess
                 probes += 1;
                 if (lightcone_positive(rec(D - 1), rx, ry, rz))
                     lo = D - 1;

@@ -26,29 +26,43 @@ struct LdsRec {
     __device__ double4 operator()(int b) const { return base[b]; }
 };
 
+// sqrt of a positive normal double from the hardware reciprocal square
+// root: one Goldschmidt step and a final Newton correction (about one
+// unit in the last place; no special-value handling, x > 0 here).
+__device__ inline double sqrt_pos(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double sq = x * y;
+    double h = 0.5 * y;
+    double r = __builtin_fma(-sq, h, 0.5);
+    sq = __builtin_fma(sq, r, sq);
+    h = __builtin_fma(h, r, h);
+    r = __builtin_fma(-sq, sq, x);
+    return __builtin_fma(r, h, sq);
+}
+
 // Retarded root, reconstruction and LW field of one pair (Eqs. dt,
-// linear, linear2, LW_E, LW_B).  w1 = {x, y, z, L1} is the bracket's older
-// sample with L1 = c (t - t_1); v1, v2 = {v, T} the velocity records of the
-// bracket ends.  Writes E and B into f[0..5].  Returns false on a numerical
-// failure (negative discriminant or eta <= 0).
-__device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, double4 v1, double4 v2, bool before,
-                               double kq, double f[6])
+// linear, linear2, LW_E, LW_B).  w1 = {x, y, z, -} is the bracket's older
+// sample, L1 = c (t - t_1); v1 = {v_1, 1/(t_2 - t_1)}, v2 = {v_2, -} the
+// velocity records of the bracket ends.  Writes E and B into f[0..5].
+// Returns false on a numerical failure (negative discriminant, eta <= 0).
+__device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, double L1, double4 v1, double4 v2,
+                               bool before, double kq, double f[6])
 {
     const double c = kC_LIGHT;
     const double c2 = c * c;
     double dx = rx - w1.x, dy = ry - w1.y, dz = rz - w1.z;
-    double L1 = w1.w;
-    // C2 dt^2 + C1 dt + C0 = 0 (Eq. dt); physical root in Vieta's form.
+    // C2 dt^2 + 2 C1h dt + C0 = 0 (Eq. dt with C1 = 2 C1h); the physical
+    // root -(C1h + sqrt(C1h^2 - C2 C0))/C2 in Vieta's form.
     double C2 = c2 - (v1.x * v1.x + v1.y * v1.y + v1.z * v1.z);
-    double dv = dx * v1.x + dy * v1.y + dz * v1.z;
-    double C1 = 2.0 * (dv - c * L1);
+    double C1h = (dx * v1.x + dy * v1.y + dz * v1.z) - c * L1;
     double C0 = L1 * L1 - (dx * dx + dy * dy + dz * dz);
-    double disc = C1 * C1 - 4.0 * C2 * C0;
-    bool ok = disc >= 0.0;
-    double sq = sqrt(fmax(disc, 0.0));
-    double dtr = 2.0 * C0 * rcp64(sq - C1);
+    double disc = C1h * C1h - C2 * C0;
+    bool ok = disc > 0.0;
+    double sq = sqrt_pos(ok ? disc : 1.0);
+    double dtr = C0 * rcp64(sq - C1h);
     // reconstruction: w = w1 + v1 dt; v = v1 + (v2 - v1) df; a = (v2 - v1)/h
-    double inv_h = before ? 0.0 : rcp64(v2.w - v1.w);
+    double inv_h = before ? 0.0 : v1.w;
     double gx = v2.x - v1.x, gy = v2.y - v1.y, gz = v2.z - v1.z;
     double ax = gx * inv_h, ay = gy * inv_h, az = gz * inv_h;  // zero out of history
     double df = dtr * inv_h;
@@ -56,16 +70,16 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
     double ex = dx - v1.x * dtr, ey = dy - v1.y * dtr, ez = dz - v1.z * dtr;  // eta
     // |eta| = c (t - t_r) on the reconstructed segment
     double en = L1 - c * dtr;
-    ok = ok && (en > 0.0);
-    double ien = rcp64(en);
+    double ev = c * en - (ex * vrx + ey * vry + ez * vrz);  // eta . v'
+    ok = ok && (en > 0.0) && (ev > 0.0);
+    double inv = rcp64(en * ev);
+    double ien = ev * inv, iev = en * inv;
     double hx = ex * ien, hy = ey * ien, hz = ez * ien;
     double px = c * hx - vrx, py = c * hy - vry, pz = c * hz - vrz;  // v'
-    double ev = c * en - (ex * vrx + ey * vry + ez * vrz);            // eta . v'
     double vv = vrx * vrx + vry * vry + vrz * vrz;
     // eta x (v' x a)
     double qx = py * az - pz * ay, qy = pz * ax - px * az, qz = px * ay - py * ax;
     double rdx = ey * qz - ez * qy, rdy = ez * qx - ex * qz, rdz = ex * qy - ey * qx;
-    double iev = rcp64(ev);
     double pref = kq * en * (iev * iev * iev);
     double cv = c2 - vv;
     double Ex = pref * (cv * px + rdx);
@@ -120,6 +134,13 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
     int64_t fail_j = 0;
     const float inv_cdt = (float)(1.0 / (kC_LIGHT * p.dt));
 
+    // light distance of every logical slot, shared by all sources
+    double *Ls = reinterpret_cast<double *>(lds + S * D);
+    for (int b = tid; b < D; b += kBlock) {
+        int ph = p.head - b;
+        ph += ph < 0 ? D : 0;
+        Ls[b] = kC_LIGHT * (p.t - p.T[ph]);
+    }
     for (int64_t jt = j0; jt < j1; jt += S) {
         const int ns = (int)((j1 - jt) < S ? (j1 - jt) : S);
         __syncthreads();
@@ -129,7 +150,8 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
                 int ph = p.head - b;
                 ph += ph < 0 ? D : 0;
                 double4 w = src[ph];
-                w.w = kC_LIGHT * (p.t - p.T[ph]);
+                double L = Ls[b];
+                w.w = L * L;
                 lds[s * D + b] = w;
             }
         }
@@ -162,31 +184,32 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
             // in lockstep (extra halvings of a one-step bracket change
             // nothing).
             bool inside[S];
-            int lo[S], hi[S];
+            int xb[S];  // f(xb) <= 0; the bracket lies in (xb, xb + n]
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 inside[s] = lightcone_positive(lds[s * D + D - 1], rx, ry, rz);
-                lo[s] = D - 1;
-                hi[s] = 0;
+                xb[s] = 0;
             }
             bool any = false;
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 any = any || (inside[s] && valid[s]);
             if (__any(any)) {
-                for (int it = 0; it < p.nit; ++it) {
+                // halving widths depend on D only: uniform across lanes
+                for (int n = D - 1; n > 1;) {
+                    const int half = n >> 1;
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        int mid = (lo[s] + hi[s]) >> 1;
-                        bool f = lightcone_positive(lds[s * D + mid], rx, ry, rz);
-                        lo[s] = f ? mid : lo[s];
-                        hi[s] = f ? hi[s] : mid;
+                        int m = xb[s] + half;
+                        bool f = lightcone_positive(lds[s * D + m], rx, ry, rz);
+                        xb[s] = f ? xb[s] : m;
                     }
+                    n -= half;
                 }
             }
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                bk[s] = inside[s] ? lo[s] : -1;
+                bk[s] = inside[s] ? xb[s] + 1 : -1;
                 if (COUNT && valid[s])
                     probes += inside[s] ? 1 + p.nit : 1;
             }
@@ -224,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
             const bool before = bk[s] < 0;
             const int bb = before ? D - 1 : bk[s];
             double f[6];
-            bool ok = lw_pair(rx, ry, rz, lds[s * D + bb], v1[s], v2[s], before, p.kq, f);
+            bool ok = lw_pair(rx, ry, rz, lds[s * D + bb], Ls[bb], v1[s], v2[s], before, p.kq, f);
             if (valid[s]) {
                 if (ok) {
 #pragma unroll
@@ -275,14 +298,15 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
 }
 
 // Sources per LDS tile for a history depth: two when two histories fit in
-// 64 KiB, else one (depths up to 4096 use up to 128 KiB).
+// 64 KiB, else one (depths up to 4096 use up to 136 KiB with the slot
+// light distances).
 int pair_fp64_tile(int D) { return D <= 1024 ? 2 : 1; }
 
 // Host-side launcher (called from the C ABI layer).
 hipError_t launch_pair_fp64(const PairParams &p, hipStream_t stream, bool kstar, bool count)
 {
     dim3 grid((unsigned)((p.m + kBlock - 1) / kBlock), (unsigned)p.nsplit);
-    size_t lds = (size_t)p.tile * p.D * sizeof(double4);
+    size_t lds = (size_t)p.tile * p.D * sizeof(double4) + (size_t)p.D * sizeof(double);
 #define EMPP_LAUNCH(K, C, G, S)                                                                              \
     do {                                                                                                    \
         if (lds > 65536)                                                                                    \

@@ -113,12 +113,13 @@ __global__ void push_kernel(PushParams p)
     const double c = kC_LIGHT;
     double g = sqrt(1.0 + (ux * ux + uy * uy + uz * uz) / (c * c));
     double ig = 1.0 / g;
-    // velocity records carry their slot time in .w
-    double4 vn = make_double4(ux * ig, uy * ig, uz * ig, p.t_now);
+    // velocity records carry 1/(T_{k+1} - T_k) of their segment in .w
+    // (0 for the newest slot, which has no segment yet)
+    double4 vn = make_double4(ux * ig, uy * ig, uz * ig, 1.0 / (p.t_next - p.t_now));
     p.ring_v[i * D + p.head] = vn;
     int nh = p.head + 1 == D ? 0 : p.head + 1;
     p.ring_w[i * D + nh] = make_double4(y.x + vn.x * p.dt, y.y + vn.y * p.dt, y.z + vn.z * p.dt, 0.0);
-    vn.w = p.t_next;
+    vn.w = 0.0;
     p.ring_v[i * D + nh] = vn;
     if (i == 0)
         p.T[nh] = p.t_next;
@@ -144,7 +145,8 @@ __global__ void init_straight_kernel(double4 *ring_w, double4 *ring_v, double *T
     int64_t k = (int64_t)s - (D - 1);
     double kdt = (double)k * dt;
     ring_w[idx] = make_double4(r[i] + vx * kdt, r[N + i] + vy * kdt, r[2 * N + i] + vz * kdt, 0.0);
-    ring_v[idx] = make_double4(vx, vy, vz, t0 + kdt);
+    double inv_h = s + 1 < D ? 1.0 / ((t0 + (double)(k + 1) * dt) - (t0 + kdt)) : 0.0;
+    ring_v[idx] = make_double4(vx, vy, vz, inv_h);
     if (i == 0)
         T[s] = t0 + kdt;
 }
@@ -162,7 +164,8 @@ __global__ void history_to_ring_kernel(const double *w, const double *v, const d
     const double *ws = w + s * 3 * N;
     const double *vs = v + s * 3 * N;
     ring_w[idx] = make_double4(ws[i], ws[N + i], ws[2 * N + i], 0.0);
-    ring_v[idx] = make_double4(vs[i], vs[N + i], vs[2 * N + i], T[s]);
+    double inv_h = s + 1 < D ? 1.0 / (T[s + 1] - T[s]) : 0.0;
+    ring_v[idx] = make_double4(vs[i], vs[N + i], vs[2 * N + i], inv_h);
 }
 
 // Ring -> [D][3][N] oldest first (logical order).
