@@ -26,17 +26,17 @@ __device__ inline bool lightcone_positive(double4 rec, double rx, double ry, dou
 // Works in "back" offsets b (0 = newest).  Because f_k decreases strictly
 // along the history, the bracket found is the unique one:
 // b* = min { b : f_b > 0 }.  Returns b* or -1 (before the history).
-template <typename Rec>
-__device__ inline int search_bisect(Rec rec, int D, double rx, double ry, double rz, int &probes)
+template <typename Test>
+__device__ __forceinline__ int search_bisect(Test test, int D, int &probes)
 {
     probes += 1;
-    if (!lightcone_positive(rec(D - 1), rx, ry, rz))
+    if (!test(D - 1))
         return -1;
     int lo = D - 1, hi = 0;  // f(lo) > 0, f(hi) <= 0 (newest: t - T = 0)
     while (lo - hi > 1) {
         int mid = (lo + hi) >> 1;
         probes += 1;
-        if (lightcone_positive(rec(mid), rx, ry, rz))
+        if (test(mid))
             lo = mid;
         else
             hi = mid;
@@ -51,18 +51,17 @@ __device__ inline int search_bisect(Rec rec, int D, double rx, double ry, double
 // search_bisect for any guess.  A non-finite guess or more than
 // max_gallop doublings falls back to plain bisection of what is left
 // (counted in fallbacks).
-template <typename Rec>
-__device__ inline int search_guided(Rec rec, int D, double rx, double ry, double rz, float guess,
-                                    int max_gallop, int &probes, int &fallback)
+template <typename Test>
+__device__ __forceinline__ int search_guided(Test test, int D, float guess, int max_gallop, int &probes, int &fallback)
 {
     if (!(guess == guess) || !(fabsf(guess) < 1e9f)) {
         fallback = 1;
-        return search_bisect(rec, D, rx, ry, rz, probes);
+        return search_bisect(test, D, probes);
     }
     int g = (int)ceilf(guess);
     g = g < 1 ? 1 : (g > D - 1 ? D - 1 : g);
-    const bool fg = lightcone_positive(rec(g), rx, ry, rz);
-    const bool fg1 = g > 1 && lightcone_positive(rec(g - 1), rx, ry, rz);  // b = 0 is never inside
+    const bool fg = test(g);
+    const bool fg1 = g > 1 && test(g - 1);  // b = 0 is never inside
     probes += g > 1 ? 2 : 1;
     if (fg && !fg1)
         return g;
@@ -76,7 +75,7 @@ __device__ inline int search_guided(Rec rec, int D, double rx, double ry, double
             if (cand <= 0)
                 break;  // hi = 0 (newest sample is never inside)
             probes += 1;
-            if (lightcone_positive(rec(cand), rx, ry, rz)) {
+            if (test(cand)) {
                 lo = cand;
             } else {
                 hi = cand;
@@ -100,14 +99,14 @@ __device__ inline int search_guided(Rec rec, int D, double rx, double ry, double
                 if (hi == D - 1)
                     return -1;  // the oldest sample was the guess
                 probes += 1;
-                if (lightcone_positive(rec(D - 1), rx, ry, rz))
+                if (test(D - 1))
                     lo = D - 1;
                 else
                     return -1;
                 break;
             }
             probes += 1;
-            if (lightcone_positive(rec(cand), rx, ry, rz)) {
+            if (test(cand)) {
                 lo = cand;
                 break;
             }
@@ -119,7 +118,7 @@ __device__ inline int search_guided(Rec rec, int D, double rx, double ry, double
     while (lo - hi > 1) {
         int mid = (lo + hi) >> 1;
         probes += 1;
-        if (lightcone_positive(rec(mid), rx, ry, rz))
+        if (test(mid))
             lo = mid;
         else
             hi = mid;

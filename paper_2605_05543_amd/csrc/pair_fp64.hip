@@ -21,11 +21,6 @@ namespace empp {
 
 namespace {
 
-struct LdsRec {
-    const double4 *base;
-    __device__ double4 operator()(int b) const { return base[b]; }
-};
-
 // sqrt of a positive normal double from the hardware reciprocal square
 // root: one Goldschmidt step and a final Newton correction (about one
 // unit in the last place; no special-value handling, x > 0 here).
@@ -219,12 +214,13 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
                 bk[s] = -1;
                 if (!valid[s])
                     continue;
-                LdsRec rec{lds + s * D};
-                double4 wn = rec(0);
+                const double4 *rec = lds + s * D;
+                auto test = [&](int b) { return lightcone_positive(rec[b], rx, ry, rz); };
+                double4 wn = rec[0];
                 double4 vn = p.ring_v[jj[s] * D + p.head];
                 float g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
                 int fb = 0;
-                bk[s] = search_guided(rec, D, rx, ry, rz, g, 6, probes, fb);
+                bk[s] = search_guided(test, D, g, 6, probes, fb);
                 nfall += fb;
             }
         }
@@ -239,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
             ph1 += ph1 < 0 ? D : 0;
             int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
             v1[s] = p.ring_v[jj[s] * D + ph1];
-            v2[s] = before ? v1[s] : p.ring_v[jj[s] * D + ph2];
+            v2[s] = p.ring_v[jj[s] * D + ph2];  // unused (inv_h = 0) out of history
         }
         double acc[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll

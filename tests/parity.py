@@ -24,3 +24,29 @@ def assert_kstar(tag, got, ref):
     bad = np.argwhere(got != ref)
     print(f"{tag}: k* pairs {got.size}, mismatches {len(bad)}, before-history {np.mean(ref < 0):.3f}", flush=True)
     assert len(bad) == 0, [(tuple(b), int(got[tuple(b)]), int(ref[tuple(b)])) for b in bad[:5]]
+
+
+# Mixed precision: max_i |dE_i| / rms_k |E_k| <= 1e-5 (and the same for B).
+MIXED_TOL = 1e-5
+
+
+def mixed_report(tag, got_E, got_B, ref_E, ref_B, SE, SB):
+    """Primary criterion plus the spread of per-target errors (stated)."""
+    out = {}
+    for name, g, r, S in (("E", got_E, ref_E, SE), ("B", got_B, ref_B, SB)):
+        d = np.linalg.norm(g - r, axis=0)
+        rms = np.sqrt(np.mean(np.sum(r * r, axis=0)))
+        rel = d / np.maximum(np.linalg.norm(r, axis=0), 1e-300)
+        out[name] = {"max_over_rms": float(d.max() / rms), "per_S_max": float(np.max(d / S)),
+                     "rel_p50": float(np.percentile(rel, 50)), "rel_p99": float(np.percentile(rel, 99)),
+                     "rel_max": float(rel.max())}
+    print(f"{tag}: " + "; ".join(f"{k} max/rms {v['max_over_rms']:.2e} max/S {v['per_S_max']:.2e} "
+                                f"rel p50 {v['rel_p50']:.1e} p99 {v['rel_p99']:.1e} max {v['rel_max']:.1e}"
+                                for k, v in out.items()), flush=True)
+    return out
+
+
+def assert_mixed(tag, got_E, got_B, ref_E, ref_B, SE, SB, tol=MIXED_TOL):
+    out = mixed_report(tag, got_E, got_B, ref_E, ref_B, SE, SB)
+    assert out["E"]["max_over_rms"] <= tol and out["B"]["max_over_rms"] <= tol, out
+    return out
