@@ -185,6 +185,8 @@ typedef struct {
     int64_t pair_launches;
     double push_ms;        /* summed duration of push-kernel launches (ms)   */
     int64_t push_launches;
+    double guess_ms;       /* summed duration of surrogate-guess launches    */
+    int64_t guess_launches;
 } empp_timing;
 
 /* Kernel timing with HIP events recorded on the context's stream around
@@ -192,6 +194,54 @@ typedef struct {
  * returns the sums since the last call (or enable) and resets them.      */
 empp_status empp_set_timing(empp_ctx *ctx, int32_t enable);
 empp_status empp_get_timing(empp_ctx *ctx, empp_timing *out);
+
+/* ---- surrogate network (retarded-delay guess) ----------------------------
+ * A 10 -> 128 -> 128 -> 1 SiLU network with BF16 weights on the matrix
+ * cores (FP32 accumulation) predicts z = log(c (t - t_r) / |r - w_n|) of a
+ * (target, source) pair from 10 features: (r - w_n)/sigma_ref (3), the
+ * source's newest velocity / c (3), its displacement over the last 4 steps
+ * / (c (T_n - T_{n-4})) (3) and log1p((t - T_n)/dt) (1).  With guess mode
+ * EMPP_GUESS_MLP it is evaluated once per (group of 64 consecutive targets
+ * in the spatial order, source) at the group centroid and scaled by each
+ * target's own distance; the exact search then finishes every bracket, so
+ * the network changes cost, never results.  Not part of the paper's
+ * method.  Parameters: the flat vector W1[128][10], b1[128], W2[128][128],
+ * b2[128], W3[128], b3 (18049 floats, FP32 masters).                     */
+typedef struct {
+    int64_t steps;         /* optimizer steps                                */
+    int32_t batch;         /* rows per step, a multiple of 64                */
+    float lr;              /* initial Adam learning rate                     */
+    float lr_final;        /* cosine decay to this rate at the last step     */
+} empp_train_cfg;
+
+typedef struct {
+    double loss_first;     /* mean squared error of z at the first step      */
+    double loss_last;      /* at the last step                               */
+    int64_t steps;
+    double seconds;        /* wall time of the loop (device work included)   */
+} empp_train_report;
+
+/* Install parameters (host, nparams == 18049) and sigma_ref (m).  Resets
+ * the optimizer state.                                                    */
+empp_status empp_surrogate_set(empp_ctx *ctx, const float *params, int64_t nparams, double sigma_ref);
+/* Read the FP32 master parameters back (host).                            */
+empp_status empp_surrogate_get(empp_ctx *ctx, float *params, int64_t nparams);
+/* Features X[count][10] and exact targets y[count] (host outputs) of pairs
+ * of the present state: given pairs (tgt[], src[] particle indices, host)
+ * or, with tgt == NULL, pairs drawn by splitmix64(seed + counter).         */
+empp_status empp_surrogate_samples(empp_ctx *ctx, int64_t count, uint64_t seed, const int64_t *tgt,
+                                   const int64_t *src, float *X, float *y);
+/* Drawn pairs written to caller-owned device buffers (asynchronous).      */
+empp_status empp_surrogate_samples_dev(empp_ctx *ctx, int64_t count, uint64_t seed, float *X_dev, float *y_dev);
+/* z for feature rows X[count][10] (host in, host out).                    */
+empp_status empp_surrogate_forward(empp_ctx *ctx, const float *X, int64_t count, float *z);
+/* Mean squared error of z against y and its gradient[18049] (host).       */
+empp_status empp_surrogate_loss_grad(empp_ctx *ctx, const float *X, const float *y, int64_t count, double *loss,
+                                     float *grad);
+/* Adam training on device rows (X_dev[count][10], y_dev[count]), cycling
+ * through them in order, batch rows per step.  Synchronous.              */
+empp_status empp_surrogate_train(empp_ctx *ctx, const float *X_dev, const float *y_dev, int64_t count,
+                                 const empp_train_cfg *cfg, empp_train_report *out);
 
 /* Wait for the context's stream and report latched device errors.        */
 empp_status empp_sync(empp_ctx *ctx);

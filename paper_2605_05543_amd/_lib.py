@@ -26,7 +26,10 @@ EXPORTS = [
     "empp_init_history_straight", "empp_set_history", "empp_step", "empp_fields_at", "empp_fields_at_dev",
     "empp_get_state", "empp_get_history", "empp_get_fields", "empp_get_diag", "empp_set_counting",
     "empp_get_counters", "empp_sync", "empp_set_mode", "empp_set_timing", "empp_get_timing",
+    "empp_surrogate_set", "empp_surrogate_get", "empp_surrogate_samples", "empp_surrogate_samples_dev",
+    "empp_surrogate_forward", "empp_surrogate_loss_grad", "empp_surrogate_train",
 ]
+N_PARAMS = 18049
 
 
 class EmppError(RuntimeError):
@@ -59,7 +62,17 @@ class Counters(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("pair_ms", ctypes.c_double), ("pair_launches", ctypes.c_int64), ("push_ms", ctypes.c_double),
-                ("push_launches", ctypes.c_int64)]
+                ("push_launches", ctypes.c_int64), ("guess_ms", ctypes.c_double), ("guess_launches", ctypes.c_int64)]
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("lr_final", ctypes.c_float)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("seconds", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -99,6 +112,13 @@ def _load():
         "empp_set_mode": [_P, _I32, _I32],
         "empp_set_timing": [_P, _I32],
         "empp_get_timing": [_P, ctypes.POINTER(Timing)],
+        "empp_surrogate_set": [_P, _P, _I64, _D],
+        "empp_surrogate_get": [_P, _P, _I64],
+        "empp_surrogate_samples": [_P, _I64, ctypes.c_uint64, _P, _P, _P, _P],
+        "empp_surrogate_samples_dev": [_P, _I64, ctypes.c_uint64, _P, _P],
+        "empp_surrogate_forward": [_P, _P, _I64, _P],
+        "empp_surrogate_loss_grad": [_P, _P, _P, _I64, ctypes.POINTER(_D), _P],
+        "empp_surrogate_train": [_P, _P, _P, _I64, ctypes.POINTER(TrainCfg), ctypes.POINTER(TrainReport)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -227,7 +247,57 @@ def empp_get_timing(h):
     t = Timing()
     _check(lib.empp_get_timing(h, ctypes.byref(t)))
     return {"pair_ms": t.pair_ms, "pair_launches": t.pair_launches, "push_ms": t.push_ms,
-            "push_launches": t.push_launches}
+            "push_launches": t.push_launches, "guess_ms": t.guess_ms, "guess_launches": t.guess_launches}
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def empp_surrogate_set(h, params, sigma_ref):
+    params = _f32(params)
+    _check(lib.empp_surrogate_set(h, _ptr(params), params.size, float(sigma_ref)))
+
+
+def empp_surrogate_get(h):
+    out = np.zeros(N_PARAMS, np.float32)
+    _check(lib.empp_surrogate_get(h, _ptr(out), N_PARAMS))
+    return out
+
+
+def empp_surrogate_samples(h, count, seed=0, tgt=None, src=None):
+    X = np.zeros((count, 10), np.float32)
+    y = np.zeros(count, np.float32)
+    t = None if tgt is None else np.ascontiguousarray(tgt, dtype=np.int64)
+    s_ = None if src is None else np.ascontiguousarray(src, dtype=np.int64)
+    _check(lib.empp_surrogate_samples(h, int(count), int(seed), _ptr(t), _ptr(s_), _ptr(X), _ptr(y)))
+    return X, y
+
+
+def empp_surrogate_samples_dev(h, count, seed, X_ptr, y_ptr):
+    _check(lib.empp_surrogate_samples_dev(h, int(count), int(seed), X_ptr, y_ptr))
+
+
+def empp_surrogate_forward(h, X):
+    X = _f32(X)
+    z = np.zeros(X.shape[0], np.float32)
+    _check(lib.empp_surrogate_forward(h, _ptr(X), X.shape[0], _ptr(z)))
+    return z
+
+
+def empp_surrogate_loss_grad(h, X, y):
+    X, y = _f32(X), _f32(y)
+    g = np.zeros(N_PARAMS, np.float32)
+    loss = _D()
+    _check(lib.empp_surrogate_loss_grad(h, _ptr(X), _ptr(y), X.shape[0], ctypes.byref(loss), _ptr(g)))
+    return loss.value, g
+
+
+def empp_surrogate_train(h, X_ptr, y_ptr, count, steps, batch, lr, lr_final):
+    cfg = TrainCfg(steps=int(steps), batch=int(batch), lr=float(lr), lr_final=float(lr_final))
+    rep = TrainReport()
+    _check(lib.empp_surrogate_train(h, X_ptr, y_ptr, int(count), ctypes.byref(cfg), ctypes.byref(rep)))
+    return {"loss_first": rep.loss_first, "loss_last": rep.loss_last, "steps": rep.steps, "seconds": rep.seconds}
 
 
 def empp_sync(h):
@@ -325,6 +395,37 @@ class Context:
 
     def timing(self):
         return empp_get_timing(self.h)
+
+    # -- surrogate network ---------------------------------------------------
+    def surrogate_set(self, params, sigma_ref):
+        empp_surrogate_set(self.h, params, sigma_ref)
+
+    def surrogate_get(self):
+        return empp_surrogate_get(self.h)
+
+    def surrogate_samples(self, count, seed=0, tgt=None, src=None):
+        return empp_surrogate_samples(self.h, count, seed, tgt, src)
+
+    def surrogate_forward(self, X):
+        return empp_surrogate_forward(self.h, X)
+
+    def surrogate_loss_grad(self, X, y):
+        return empp_surrogate_loss_grad(self.h, X, y)
+
+    def surrogate_train_torch(self, X, y, steps, batch, lr=1e-3, lr_final=1e-5):
+        """Train on torch device tensors X [count, 10], y [count] (float32)."""
+        assert X.is_cuda and X.dtype.itemsize == 4 and X.is_contiguous() and y.is_contiguous()
+        return empp_surrogate_train(self.h, X.data_ptr(), y.data_ptr(), X.shape[0], steps, batch, lr, lr_final)
+
+    def surrogate_samples_torch(self, count, seed):
+        """Drawn training pairs of the present state as torch device tensors."""
+        import torch
+
+        X = torch.empty((count, 10), dtype=torch.float32, device=self._ws.device)
+        y = torch.empty(count, dtype=torch.float32, device=self._ws.device)
+        empp_surrogate_samples_dev(self.h, count, seed, X.data_ptr(), y.data_ptr())
+        self.sync()
+        return X, y
 
     def set_mode(self, precision, guess):
         empp_set_mode(self.h, precision, guess)

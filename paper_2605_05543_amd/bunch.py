@@ -178,3 +178,20 @@ def uniform_history(ns, dt, w_now, vel, t_now=0.0):
     w = w_now[None] + vel[None] * (T - t_now)[:, None, None]
     v = np.broadcast_to(vel[None], w.shape).copy()
     return T, w, v
+
+
+def surrogate_init(seed=4):
+    """Initial parameters of the 10 -> 128 -> 128 -> 1 surrogate network in
+    its flat layout (W1[128][10], b1, W2[128][128], b2, W3[128], b3): weights
+    uniform in +-1/sqrt(fan_in), biases zero; float32."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, 128 * 10) / np.sqrt(10.0), np.zeros(128),
+             rng.uniform(-1, 1, 128 * 128) / np.sqrt(128.0), np.zeros(128),
+             rng.uniform(-1, 1, 128) / np.sqrt(128.0), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def sigma_ref_of(r):
+    """Reference length (sigma_x sigma_y sigma_z)^(1/3) of a bunch r[3, N]."""
+    s = r.std(axis=1)
+    return float(np.prod(s) ** (1.0 / 3.0))

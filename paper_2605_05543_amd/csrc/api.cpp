@@ -11,8 +11,11 @@
 #include <string>
 #include <vector>
 
+#include <chrono>
+
 #include "empp.h"
 #include "empp_dev.h"
+#include "mlp_dev.h"
 
 namespace empp {
 int pair_fp64_tile(int D);
@@ -28,6 +31,19 @@ hipError_t launch_ring_to_history(const double4 *rw, const double4 *rv, double *
                                   int head, hipStream_t s);
 hipError_t launch_newest_positions(const double4 *rw, double *r, int64_t N, int D, int head, hipStream_t s);
 hipError_t launch_diag(const double4 *rw, const double *u, int64_t N, int D, int head, double *out, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpPacked *net, const float *X, int64_t n, float *z, hipStream_t s);
+hipError_t launch_mlp_train(const MlpPacked *net, const float *X, const float *y, int64_t n, float scale,
+                            float *part, int nblocks, hipStream_t s);
+hipError_t launch_mlp_reduce(const float *part, int nblocks, float *grad, hipStream_t s);
+hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *grad, int64_t step, float lr,
+                           hipStream_t s);
+hipError_t launch_mlp_pack(const float *master, MlpPacked *net, hipStream_t s);
+hipError_t launch_mlp_sample(const SampleParams &p, const int64_t *tgt, const int64_t *src, int64_t count, float *X,
+                             float *y, hipStream_t s);
+hipError_t launch_mlp_group_guess(const MlpPacked *net, const GuessParams &p, float *G, hipStream_t s);
+hipError_t launch_group_centroid(const double4 *ring_w, const int32_t *order, int64_t N, int D, int head,
+                                 double3 *centroid, hipStream_t s);
+hipError_t launch_group_centroid_x(const double *x, int64_t m, double3 *centroid, hipStream_t s);
 }  // namespace empp
 
 using namespace empp;
@@ -213,7 +229,18 @@ struct empp_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    std::vector<std::pair<size_t, int>> ev_marks;  // (start index, kind 0 pair / 1 push)
+    std::vector<std::pair<size_t, int>> ev_marks;  // (start index, kind 0 pair / 1 push / 2 guess)
+    // surrogate network (device buffers allocated by empp_surrogate_set)
+    struct {
+        float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *part = nullptr;
+        MlpPacked *net = nullptr;
+        float *G = nullptr;
+        double3 *cent = nullptr;
+        int part_blocks = 512;
+        int64_t adam_step = 0;
+        double sigma_ref = 0.0;
+        bool ready = false;
+    } sg;
 
     template <typename Tp>
     Tp *at(uint64_t off) const { return reinterpret_cast<Tp *>(ws + off); }
@@ -320,8 +347,40 @@ hipError_t timed(empp_ctx *ctx, int kind, F &&launch)
     return e;
 }
 
-hipError_t launch_pair(empp_ctx *ctx, const PairParams &p, bool kstar)
+// Surrogate guesses for a launch of m targets (external x or the
+// particles in spatial order): group centroids, then one network evaluation
+// per (group, source).
+hipError_t launch_guesses(empp_ctx *ctx, PairParams &p)
 {
+    if (ctx->cfg.guess != EMPP_GUESS_MLP)
+        return hipSuccess;
+    return timed(ctx, 2, [&]() {
+        hipError_t e = p.x ? launch_group_centroid_x(p.x, p.m, ctx->sg.cent, ctx->stream)
+                           : launch_group_centroid(ctx->ring_w(), p.order, p.m, ctx->cfg.depth, ctx->head,
+                                                   ctx->sg.cent, ctx->stream);
+        if (e != hipSuccess)
+            return e;
+        GuessParams gp{};
+        gp.ring_w = ctx->ring_w();
+        gp.ring_v = ctx->ring_v();
+        gp.T = ctx->T();
+        gp.centroid = ctx->sg.cent;
+        gp.N = ctx->cfg.n;
+        gp.ngroups = (p.m + 63) / 64;
+        gp.D = ctx->cfg.depth;
+        gp.head = ctx->head;
+        gp.inv_sigma = 1.0 / ctx->sg.sigma_ref;
+        p.G = ctx->sg.G;
+        p.g_shift = 6;
+        return launch_mlp_group_guess(ctx->sg.net, gp, ctx->sg.G, ctx->stream);
+    });
+}
+
+hipError_t launch_pair(empp_ctx *ctx, PairParams &p, bool kstar)
+{
+    hipError_t eg = launch_guesses(ctx, p);
+    if (eg != hipSuccess)
+        return eg;
     return timed(ctx, 0, [&]() {
         if (ctx->cfg.precision == EMPP_MIXED)
             return launch_pair_mixed(p, ctx->stream, kstar, ctx->counting);
@@ -409,6 +468,10 @@ void empp_destroy(empp_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     for (hipEvent_t e : ctx->ev_pool)
         (void)hipEventDestroy(e);
+    for (void *p : {(void *)ctx->sg.master, (void *)ctx->sg.m, (void *)ctx->sg.v, (void *)ctx->sg.grad,
+                    (void *)ctx->sg.part, (void *)ctx->sg.net, (void *)ctx->sg.G, (void *)ctx->sg.cent})
+        if (p)
+            (void)hipFree(p);
     if (ctx->owns_ws && ctx->ws)
         (void)hipFree(ctx->ws);
     delete ctx;
@@ -528,6 +591,8 @@ empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
         return fail(EMPP_ESTATE, "step before the history is initialised");
     if (ctx->handed_off)
         return fail(EMPP_ESTATE, "step after handoff (use transport)");
+    if (ctx->cfg.guess == EMPP_GUESS_MLP && !ctx->sg.ready)
+        return fail(EMPP_ESTATE, "guess mode MLP without a surrogate network (empp_surrogate_set)");
     empp_status st = set_device(ctx);
     if (st != EMPP_OK)
         return st;
@@ -633,6 +698,8 @@ static empp_status fields_precheck(empp_ctx *ctx, double t, int64_t m)
         return fail(EMPP_EINVAL, "m < 0");
     if (t != ctx->t_now)
         return fail(EMPP_EINVAL, "t = %.17g is not the present time %.17g", t, ctx->t_now);
+    if (ctx->cfg.guess == EMPP_GUESS_MLP && !ctx->sg.ready)
+        return fail(EMPP_ESTATE, "guess mode MLP without a surrogate network (empp_surrogate_set)");
     return set_device(ctx);
 }
 
@@ -893,13 +960,270 @@ empp_status empp_get_timing(empp_ctx *ctx, empp_timing *out)
         if (mk.second == 0) {
             out->pair_ms += ms;
             out->pair_launches += 1;
-        } else {
+        } else if (mk.second == 1) {
             out->push_ms += ms;
             out->push_launches += 1;
+        } else {
+            out->guess_ms += ms;
+            out->guess_launches += 1;
         }
     }
     ctx->ev_used = 0;
     ctx->ev_marks.clear();
+    return EMPP_OK;
+}
+
+static empp_status surrogate_alloc(empp_ctx *ctx)
+{
+    if (ctx->sg.master)
+        return EMPP_OK;
+    const int64_t N = ctx->cfg.n;
+    const int64_t ng = (N + 63) / 64;
+    struct {
+        void **p;
+        size_t bytes;
+    } want[] = {
+        {(void **)&ctx->sg.master, kParams * sizeof(float)},
+        {(void **)&ctx->sg.m, kParams * sizeof(float)},
+        {(void **)&ctx->sg.v, kParams * sizeof(float)},
+        {(void **)&ctx->sg.grad, (kParams + 1) * sizeof(float)},
+        {(void **)&ctx->sg.part, (size_t)ctx->sg.part_blocks * (kParams + 1) * sizeof(float)},
+        {(void **)&ctx->sg.net, sizeof(MlpPacked)},
+        {(void **)&ctx->sg.G, (size_t)ng * N * sizeof(float)},
+        {(void **)&ctx->sg.cent, (size_t)ng * sizeof(double3)},
+    };
+    for (auto &w : want) {
+        hipError_t e = hipMalloc(w.p, w.bytes);
+        if (e != hipSuccess)
+            return fail(EMPP_ENOMEM, "hipMalloc(%zu) for the surrogate failed: %s", w.bytes, hipGetErrorString(e));
+    }
+    return EMPP_OK;
+}
+
+empp_status empp_surrogate_set(empp_ctx *ctx, const float *params, int64_t nparams, double sigma_ref)
+{
+    if (!ctx || !params)
+        return fail(EMPP_EINVAL, "NULL argument");
+    if (nparams != kParams)
+        return fail(EMPP_EINVAL, "nparams %lld != %d", (long long)nparams, kParams);
+    if (!(sigma_ref > 0.0) || !std::isfinite(sigma_ref))
+        return fail(EMPP_EINVAL, "sigma_ref must be positive");
+    for (int64_t i = 0; i < nparams; ++i)
+        if (!std::isfinite(params[i]))
+            return fail(EMPP_EINVAL, "non-finite parameter %lld", (long long)i);
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK || (st = surrogate_alloc(ctx)) != EMPP_OK)
+        return st;
+    HIP_TRY(hipMemcpyAsync(ctx->sg.master, params, kParams * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->sg.m, 0, kParams * sizeof(float), ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->sg.v, 0, kParams * sizeof(float), ctx->stream));
+    HIP_TRY(launch_mlp_pack(ctx->sg.master, ctx->sg.net, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->sg.adam_step = 0;
+    ctx->sg.sigma_ref = sigma_ref;
+    ctx->sg.ready = true;
+    return EMPP_OK;
+}
+
+empp_status empp_surrogate_get(empp_ctx *ctx, float *params, int64_t nparams)
+{
+    if (!ctx || !params)
+        return fail(EMPP_EINVAL, "NULL argument");
+    if (nparams != kParams)
+        return fail(EMPP_EINVAL, "nparams %lld != %d", (long long)nparams, kParams);
+    if (!ctx->sg.ready)
+        return fail(EMPP_ESTATE, "no surrogate network");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    HIP_TRY(hipMemcpyAsync(params, ctx->sg.master, kParams * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return EMPP_OK;
+}
+
+static SampleParams sample_params(empp_ctx *ctx, uint64_t seed)
+{
+    SampleParams sp{};
+    sp.ring_w = ctx->ring_w();
+    sp.ring_v = ctx->ring_v();
+    sp.T = ctx->T();
+    sp.N = ctx->cfg.n;
+    sp.D = ctx->cfg.depth;
+    sp.head = ctx->head;
+    sp.t = ctx->t_now;
+    sp.inv_sigma = 1.0 / ctx->sg.sigma_ref;
+    sp.seed = seed;
+    return sp;
+}
+
+static empp_status surrogate_precheck(empp_ctx *ctx, bool need_state)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    if (!ctx->sg.ready)
+        return fail(EMPP_ESTATE, "no surrogate network (empp_surrogate_set)");
+    if (need_state && (!ctx->have_history || ctx->handed_off))
+        return fail(EMPP_ESTATE, "no history to sample from");
+    if (need_state && ctx->cfg.depth < 5)
+        return fail(EMPP_EUNSUPPORTED, "features need at least 5 history slots");
+    return set_device(ctx);
+}
+
+empp_status empp_surrogate_samples_dev(empp_ctx *ctx, int64_t count, uint64_t seed, float *X_dev, float *y_dev)
+{
+    empp_status st = surrogate_precheck(ctx, true);
+    if (st != EMPP_OK)
+        return st;
+    if (count < 0 || (count > 0 && (!X_dev || !y_dev)))
+        return fail(EMPP_EINVAL, "bad sample buffers");
+    if (count == 0)
+        return EMPP_OK;
+    HIP_TRY(launch_mlp_sample(sample_params(ctx, seed), nullptr, nullptr, count, X_dev, y_dev, ctx->stream));
+    return EMPP_OK;
+}
+
+empp_status empp_surrogate_samples(empp_ctx *ctx, int64_t count, uint64_t seed, const int64_t *tgt, const int64_t *src,
+                                   float *X, float *y)
+{
+    empp_status st = surrogate_precheck(ctx, true);
+    if (st != EMPP_OK)
+        return st;
+    if (count < 0 || (count > 0 && (!X || !y)) || ((tgt == nullptr) != (src == nullptr)))
+        return fail(EMPP_EINVAL, "bad sample arguments");
+    if (count == 0)
+        return EMPP_OK;
+    const int64_t N = ctx->cfg.n;
+    if (tgt)
+        for (int64_t q = 0; q < count; ++q)
+            if (tgt[q] < 0 || tgt[q] >= N || src[q] < 0 || src[q] >= N || tgt[q] == src[q])
+                return fail(EMPP_EINVAL, "pair %lld out of range or a self pair", (long long)q);
+    size_t bytes = (size_t)count * (kIn + 1) * sizeof(float) + (tgt ? 2 * count * sizeof(int64_t) : 0) + 512;
+    char *tmp = nullptr;
+    HIP_TRY(hipMalloc((void **)&tmp, bytes));
+    float *Xd = (float *)tmp;
+    float *yd = Xd + count * kIn;
+    int64_t *td = tgt ? (int64_t *)(tmp + align_up((size_t)count * (kIn + 1) * sizeof(float))) : nullptr;
+    int64_t *sd = tgt ? td + count : nullptr;
+    auto body = [&]() -> empp_status {
+        if (tgt) {
+            HIP_TRY(hipMemcpyAsync(td, tgt, count * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+            HIP_TRY(hipMemcpyAsync(sd, src, count * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        }
+        HIP_TRY(launch_mlp_sample(sample_params(ctx, seed), td, sd, count, Xd, yd, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(X, Xd, count * kIn * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(y, yd, count * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return EMPP_OK;
+    };
+    st = body();
+    (void)hipFree(tmp);
+    return st;
+}
+
+empp_status empp_surrogate_forward(empp_ctx *ctx, const float *X, int64_t count, float *z)
+{
+    empp_status st = surrogate_precheck(ctx, false);
+    if (st != EMPP_OK)
+        return st;
+    if (count < 0 || (count > 0 && (!X || !z)))
+        return fail(EMPP_EINVAL, "bad arguments");
+    if (count == 0)
+        return EMPP_OK;
+    float *tmp = nullptr;
+    HIP_TRY(hipMalloc((void **)&tmp, (size_t)count * (kIn + 1) * sizeof(float)));
+    auto body = [&]() -> empp_status {
+        HIP_TRY(hipMemcpyAsync(tmp, X, count * kIn * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(launch_mlp_forward(ctx->sg.net, tmp, count, tmp + count * kIn, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(z, tmp + count * kIn, count * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return EMPP_OK;
+    };
+    st = body();
+    (void)hipFree(tmp);
+    return st;
+}
+
+// One gradient evaluation on device rows: partial gradients per block,
+// then their fixed-order sum into sg.grad ([kParams] gradient, then the
+// sum of squared residuals).
+static hipError_t surrogate_grad(empp_ctx *ctx, const float *X, const float *y, int64_t count)
+{
+    int nb = (int)std::min<int64_t>(ctx->sg.part_blocks, (count + 63) / 64);
+    hipError_t e = launch_mlp_train(ctx->sg.net, X, y, count, 2.0f / (float)count, ctx->sg.part, nb, ctx->stream);
+    if (e == hipSuccess)
+        e = launch_mlp_reduce(ctx->sg.part, nb, ctx->sg.grad, ctx->stream);
+    return e;
+}
+
+empp_status empp_surrogate_loss_grad(empp_ctx *ctx, const float *X, const float *y, int64_t count, double *loss,
+                                     float *grad)
+{
+    empp_status st = surrogate_precheck(ctx, false);
+    if (st != EMPP_OK)
+        return st;
+    if (count <= 0 || !X || !y || !grad)
+        return fail(EMPP_EINVAL, "bad arguments");
+    float *tmp = nullptr;
+    HIP_TRY(hipMalloc((void **)&tmp, (size_t)count * (kIn + 1) * sizeof(float)));
+    std::vector<float> g(kParams + 1);
+    auto body = [&]() -> empp_status {
+        HIP_TRY(hipMemcpyAsync(tmp, X, count * kIn * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(tmp + count * kIn, y, count * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(surrogate_grad(ctx, tmp, tmp + count * kIn, count));
+        HIP_TRY(hipMemcpyAsync(g.data(), ctx->sg.grad, (kParams + 1) * sizeof(float), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return EMPP_OK;
+    };
+    st = body();
+    (void)hipFree(tmp);
+    if (st != EMPP_OK)
+        return st;
+    std::copy(g.begin(), g.begin() + kParams, grad);
+    if (loss)
+        *loss = (double)g[kParams] / (double)count;
+    return EMPP_OK;
+}
+
+empp_status empp_surrogate_train(empp_ctx *ctx, const float *X_dev, const float *y_dev, int64_t count,
+                                 const empp_train_cfg *cfg, empp_train_report *out)
+{
+    empp_status st = surrogate_precheck(ctx, false);
+    if (st != EMPP_OK)
+        return st;
+    if (!X_dev || !y_dev || !cfg || count <= 0)
+        return fail(EMPP_EINVAL, "bad arguments");
+    if (cfg->batch <= 0 || cfg->batch % 64 != 0 || cfg->batch > count || cfg->steps < 0 || !(cfg->lr > 0.0f))
+        return fail(EMPP_EINVAL, "bad training configuration");
+    auto t0 = std::chrono::steady_clock::now();
+    float first = 0.0f, last = 0.0f;
+    const int64_t B = cfg->batch;
+    for (int64_t s = 0; s < cfg->steps; ++s) {
+        int64_t start = (s * B) % count;
+        if (start + B > count)
+            start = 0;
+        HIP_TRY(surrogate_grad(ctx, X_dev + start * kIn, y_dev + start, B));
+        if (s == 0) {
+            HIP_TRY(hipMemcpyAsync(&first, ctx->sg.grad + kParams, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        }
+        if (s == cfg->steps - 1) {
+            HIP_TRY(hipMemcpyAsync(&last, ctx->sg.grad + kParams, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+        }
+        double frac = cfg->steps > 1 ? (double)s / (double)(cfg->steps - 1) : 1.0;
+        float lr = (float)(cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) * (1.0 + std::cos(M_PI * frac)));
+        ctx->sg.adam_step += 1;
+        HIP_TRY(launch_mlp_adam(ctx->sg.master, ctx->sg.m, ctx->sg.v, ctx->sg.grad, ctx->sg.adam_step, lr,
+                                ctx->stream));
+        HIP_TRY(launch_mlp_pack(ctx->sg.master, ctx->sg.net, ctx->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    auto t1 = std::chrono::steady_clock::now();
+    if (out) {
+        out->loss_first = (double)first / (double)B;
+        out->loss_last = (double)last / (double)B;
+        out->steps = cfg->steps;
+        out->seconds = std::chrono::duration<double>(t1 - t0).count();
+    }
     return EMPP_OK;
 }
 

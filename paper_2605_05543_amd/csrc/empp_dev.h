@@ -54,8 +54,8 @@ struct PairParams {
     int32_t guess;
     float dt_inv_f;
     double dt;
-    const void *mlp;            // packed bf16 network (mixed path)
-    double sigma_ref_inv;
+    const float *G;             // surrogate guesses: row (a >> g_shift), column source
+    int32_t g_shift;            // 6: one guess per 64 consecutive targets
 };
 
 struct PushParams {

@@ -217,8 +217,16 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
                 const double4 *rec = lds + s * D;
                 auto test = [&](int b) { return lightcone_positive(rec[b], rx, ry, rz); };
                 double4 wn = rec[0];
-                double4 vn = p.ring_v[jj[s] * D + p.head];
-                float g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
+                float g;
+                if (GUESS == 2) {
+                    double4 vn = p.ring_v[jj[s] * D + p.head];
+                    g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
+                } else {
+                    // surrogate: predicted c (t - t_r) / |r - w_n| times this target's distance
+                    float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
+                    float gh = p.G[(a >> p.g_shift) * p.n_src + jj[s]];
+                    g = gh * __builtin_amdgcn_sqrtf(Rx * Rx + Ry * Ry + Rz * Rz) * inv_cdt;
+                }
                 int fb = 0;
                 bk[s] = search_guided(test, D, g, 6, probes, fb);
                 nfall += fb;
@@ -312,8 +320,12 @@ hipError_t launch_pair_fp64(const PairParams &p, hipStream_t stream, bool kstar,
     } while (0)
 #define EMPP_BY_TILE(K, C, G) \
     do { if (p.tile == 2) EMPP_LAUNCH(K, C, G, 2); else EMPP_LAUNCH(K, C, G, 1); } while (0)
-#define EMPP_BY_GUESS(K, C) \
-    do { if (p.guess == 2) EMPP_BY_TILE(K, C, 2); else EMPP_BY_TILE(K, C, 0); } while (0)
+#define EMPP_BY_GUESS(K, C)                                                                                  \
+    do {                                                                                                    \
+        if (p.guess == 2) EMPP_BY_TILE(K, C, 2);                                                             \
+        else if (p.guess == 1) EMPP_BY_TILE(K, C, 1);                                                        \
+        else EMPP_BY_TILE(K, C, 0);                                                                          \
+    } while (0)
     if (kstar) {
         if (count) EMPP_BY_GUESS(true, true); else EMPP_BY_GUESS(true, false);
     } else {

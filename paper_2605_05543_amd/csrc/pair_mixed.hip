@@ -271,8 +271,15 @@ __global__ __launch_bounds__(kBlock) void pair_mixed_kernel(PairParams p)
                 if (!valid[s])
                     continue;
                 auto t1 = [&](int b) { return test(s, b); };
-                double4 vn = p.ring_v[jj[s] * D + p.head];
-                float g = ballistic_steps((double)Rx[s], (double)Ry[s], (double)Rz[s], vn, inv_cdt);
+                float g;
+                if (GUESS == 2) {
+                    double4 vn = p.ring_v[jj[s] * D + p.head];
+                    g = ballistic_steps((double)Rx[s], (double)Ry[s], (double)Rz[s], vn, inv_cdt);
+                } else {
+                    // surrogate: predicted c (t - t_r) / |r - w_n| times this target's distance
+                    float gh = p.G[(a >> p.g_shift) * p.n_src + jj[s]];
+                    g = gh * __builtin_amdgcn_sqrtf(Rx[s] * Rx[s] + Ry[s] * Ry[s] + Rz[s] * Rz[s]) * inv_cdt;
+                }
                 int fb = 0;
                 bk[s] = search_guided(t1, D, g, 6, probes, fb);
                 nfall += fb;
@@ -372,8 +379,12 @@ hipError_t launch_pair_mixed(const PairParams &p0, hipStream_t stream, bool ksta
         else if (p.tile == 2) EMPP_LAUNCH(K, C, G, 2);                                                       \
         else EMPP_LAUNCH(K, C, G, 1);                                                                        \
     } while (0)
-#define EMPP_BY_GUESS(K, C) \
-    do { if (p.guess != 0) EMPP_BY_TILE(K, C, 2); else EMPP_BY_TILE(K, C, 0); } while (0)
+#define EMPP_BY_GUESS(K, C)                                                                                  \
+    do {                                                                                                    \
+        if (p.guess == 2) EMPP_BY_TILE(K, C, 2);                                                             \
+        else if (p.guess == 1) EMPP_BY_TILE(K, C, 1);                                                        \
+        else EMPP_BY_TILE(K, C, 0);                                                                          \
+    } while (0)
     if (kstar) {
         if (count) EMPP_BY_GUESS(true, true); else EMPP_BY_GUESS(true, false);
     } else {

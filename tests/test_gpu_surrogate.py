@@ -1,0 +1,148 @@
+"""The surrogate network on the GPU (BF16 matrix-core kernels) against the
+FP64 oracle of oracle/mlp.py, and the guarantee that a guess never changes
+a result.
+
+Tolerances: features 1e-6 (float32 rounding of FP64 quantities); forward
+and gradient 1e-2 relative (BF16 activations on the GPU, FP64 activations
+in the oracle; the figure reached is printed); Adam 1e-6."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from paper_2605_05543_amd import bunch
+
+pytestmark = pytest.mark.gpu
+
+Q, ME, C = -bunch.E_CHARGE, bunch.M_ELECTRON, bunch.C_LIGHT
+
+
+def _ctx(n, depth, dt, guess=0, precision=0):
+    from paper_2605_05543_amd._lib import Context
+
+    return Context(n=n, depth=depth, q=Q, m=ME, dt=dt, guess=guess, precision=precision)
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.get()
+
+
+def test_samples_match_oracle(orc):
+    """Features and exact normalised delays of given pairs."""
+    print("case surrogate samples", flush=True)
+    n, D, dt = 48, 64, 1e-13
+    T, w, v = bunch.wiggly_history(n, D, dt, beta=0.9, accel_rel=0.1, seed=5)
+    sig = 1e-3
+    rng = np.random.default_rng(6)
+    tgt = rng.integers(0, n, 500)
+    src = (tgt + rng.integers(1, n, 500)) % n
+    with _ctx(n, D, dt) as ctx:
+        ctx.set_history(T, w, v, np.zeros((3, n)))
+        ctx.surrogate_set(bunch.surrogate_init(1), sig)
+        X, y = ctx.surrogate_samples(500, tgt=tgt, src=src)
+    Xo = omlp.features(w[-1][:, tgt], w[-1][:, src], v[-1][:, src], w[-5][:, src], T[-1], T[-5], T[-1], dt, sig)
+    ret = orc.retarded(T, w, v, T[-1], w[-1], np.arange(n))
+    tr = ret["tr"][tgt, src]
+    yo = np.log(omlp.normalised_delay(w[-1][:, tgt], w[-1][:, src], T[-1], tr))
+    ex = np.max(np.abs(X - Xo) / np.maximum(np.abs(Xo), 1.0))
+    ey = np.max(np.abs(y - yo))
+    print(f"   features max err {ex:.2e}, log-delay max err {ey:.2e}, delay range {np.exp(yo).min():.2f}.."
+          f"{np.exp(yo).max():.2f}", flush=True)
+    assert ex < 1e-6 and ey < 1e-6
+
+
+def test_forward_and_gradient_match_oracle():
+    print("case surrogate forward/backward", flush=True)
+    rng = np.random.default_rng(7)
+    P = bunch.surrogate_init(2)
+    X = rng.standard_normal((1000, 10)).astype(np.float32)
+    X[:, 3:9] *= 0.5
+    y = rng.standard_normal(1000).astype(np.float32)
+    with _ctx(8, 8, 1e-13) as ctx:
+        ctx.surrogate_set(P, 1e-3)
+        z = ctx.surrogate_forward(X)
+        loss, g = ctx.surrogate_loss_grad(X, y)
+    zo, _ = omlp.forward(P.astype(np.float64), X.astype(np.float64))
+    lo, go = omlp.loss_and_grad(P.astype(np.float64), X.astype(np.float64), y.astype(np.float64))
+    ez = np.max(np.abs(z - zo)) / np.max(np.abs(zo))
+    el = abs(loss - lo) / lo
+    eg = np.linalg.norm(g - go) / np.linalg.norm(go)
+    blocks = {name: np.linalg.norm(g[o:o + k] - go[o:o + k]) / np.linalg.norm(go[o:o + k])
+              for name, o, k in (("W1", 0, 1280), ("b1", 1280, 128), ("W2", 1408, 16384), ("b2", 17792, 128),
+                                 ("W3", 17920, 128), ("b3", 18048, 1))}
+    print(f"   forward max rel err {ez:.2e}; loss rel err {el:.2e}; gradient rel L2 err {eg:.2e}; "
+          + ", ".join(f"{k} {v:.1e}" for k, v in blocks.items()), flush=True)
+    assert ez < 1e-2 and el < 1e-2 and eg < 1e-2
+    assert all(v < 3e-2 for v in blocks.values())
+
+
+def test_adam_step_matches_oracle():
+    print("case surrogate adam", flush=True)
+    rng = np.random.default_rng(8)
+    P = bunch.surrogate_init(3)
+    X = rng.standard_normal((256, 10)).astype(np.float32)
+    y = rng.standard_normal(256).astype(np.float32)
+    import torch
+
+    with _ctx(8, 8, 1e-13) as ctx:
+        ctx.surrogate_set(P, 1e-3)
+        _, g = ctx.surrogate_loss_grad(X, y)
+        Xt = torch.tensor(X, device="cuda")
+        yt = torch.tensor(y, device="cuda")
+        ctx.surrogate_train_torch(Xt, yt, steps=1, batch=256, lr=1e-3, lr_final=1e-3)
+        P1 = ctx.surrogate_get()
+    Po, _, _ = omlp.adam_step(P.astype(np.float64), 0.0, 0.0, g.astype(np.float64), 1, 1e-3)
+    err = np.max(np.abs(P1 - Po))
+    print(f"   adam max abs err {err:.2e}", flush=True)
+    assert err < 1e-6
+
+
+def test_training_reduces_loss():
+    """Training pairs drawn from a C1 bunch's straight history; the loss of
+    the log-delay falls by more than 10x."""
+    print("case surrogate training", flush=True)
+    wl = bunch.C1
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    with _ctx(wl.bunch.n, wl.depth, wl.dt) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        ctx.surrogate_set(bunch.surrogate_init(4), bunch.sigma_ref_of(r))
+        X, y = ctx.surrogate_samples_torch(1 << 16, seed=11)
+        rep = ctx.surrogate_train_torch(X, y, steps=600, batch=1024, lr=3e-3, lr_final=1e-4)
+    print(f"   loss {rep['loss_first']:.3e} -> {rep['loss_last']:.3e} in {rep['steps']} steps, "
+          f"{rep['seconds']:.2f} s", flush=True)
+    assert rep["loss_last"] < 0.1 * rep["loss_first"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_guess_never_changes_results(precision):
+    """k* and the fields are bit-identical with the paper's bisection, the
+    ballistic guess, a trained and an untrained network, and a network
+    whose guesses are garbage (non-finite)."""
+    print(f"case guess invariance precision={precision}", flush=True)
+    n, D, dt = 300, 128, 1e-13
+    T, w, v = bunch.wiggly_history(n, D, dt, beta=0.9, accel_rel=0.1, seed=9)
+    rng = np.random.default_rng(10)
+    x = 1.5e-3 * rng.standard_normal((3, 257))
+    outs = {}
+    with _ctx(n, D, dt, precision=precision) as ctx:
+        ctx.set_history(T, w, v, np.zeros((3, n)))
+        ctx.surrogate_set(bunch.surrogate_init(5), 1e-3)
+        Xs, ys = ctx.surrogate_samples_torch(1 << 14, seed=3)
+        for name, guess, params in (("bisect", 0, None), ("ballistic", 2, None), ("untrained", 1, None),
+                                    ("trained", 1, "train"), ("garbage", 1, "garbage")):
+            if params == "train":
+                ctx.surrogate_train_torch(Xs, ys, steps=200, batch=1024, lr=3e-3, lr_final=1e-4)
+            elif params == "garbage":
+                ctx.surrogate_set(np.full(18049, 1e30, np.float32), 1e-3)
+            ctx.set_mode(precision, guess)
+            ctx.set_counting(True)
+            E, B, k = ctx.fields_at(T[-1], x, want_kstar=True)
+            outs[name] = (E, B, k, ctx.counters())
+    ref = outs["bisect"]
+    for name, (E, B, k, cnt) in outs.items():
+        print(f"   {name}: probes/pair {cnt['probes'] / cnt['pairs']:.2f}, fallbacks {cnt['fallbacks']}", flush=True)
+        assert np.array_equal(k, ref[2]), name
+        assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), name
+    assert outs["garbage"][3]["fallbacks"] > 0
