@@ -47,6 +47,26 @@ def algorithmic_flops(counters):
             + FLOP_BEFORE * counters["before"])
 
 
+SURROGATE_SAMPLES = 50_000_000  # training pairs, half from a C2 bunch, half from this workload's
+
+
+def train_surrogate(ctx, wl, r):
+    """Train the context's surrogate network on pairs drawn from a C2 bunch
+    and from this workload's bunch (4 steps in), before any timing."""
+    from paper_2605_05543_amd import surrogate
+
+    half = SURROGATE_SAMPLES // 2
+    s2 = surrogate.draw_samples(bunch.C2, half, seed=21)
+    ctx.step(4)
+    ctx.surrogate_set(bunch.surrogate_init(0), bunch.sigma_ref_of(r))
+    s3 = ctx.surrogate_samples_torch(half, seed=23)
+    rep = surrogate.train(ctx, [s2, s3], batch=8192)
+    del s2, s3
+    log(f"  surrogate trained on {SURROGATE_SAMPLES:.1e} pairs: loss {rep['loss_first']:.3e} -> "
+        f"{rep['loss_last']:.3e} in {rep['steps']} steps, {rep['seconds']:.2f} s")
+    return rep
+
+
 def run_path(wl, r, u, precision, guess, steps, warmup):
     import torch
 
@@ -54,9 +74,11 @@ def run_path(wl, r, u, precision, guess, steps, warmup):
 
     n = wl.bunch.n
     ctx = Context(n=n, depth=wl.depth, q=-bunch.E_CHARGE, m=bunch.M_ELECTRON, dt=wl.dt, ext_field=wl.ext_field,
-                  dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re, precision=precision, guess=guess)
+                  dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re, precision=precision, guess=0)
     ctx.init_bunch(r, u, 0.0)
     ctx.init_history_straight()
+    train_rep = train_surrogate(ctx, wl, r) if guess == 1 else None
+    ctx.set_mode(precision, guess)
     # one counting step (untimed) for the algorithmic work per launch
     ctx.set_counting(True)
     ctx.step(1)
@@ -86,7 +108,11 @@ def run_path(wl, r, u, precision, guess, steps, warmup):
         "probes_per_pair": cnt["probes"] / cnt["pairs"], "before_history_fraction": cnt["before"] / cnt["pairs"],
         "fallbacks": cnt["fallbacks"], "flops_per_pair": flops / cnt["pairs"],
         "achieved_tflops": flops / (pair_ms * 1e-3) / 1e12, "sigma_after": d["sigma"],
+        "guess_kernel_ms": tim["guess_ms"] / max(1, tim["guess_launches"]) if tim["guess_launches"] else 0.0,
+        "rescues_per_pair": cnt["rescues"] / cnt["pairs"],
     }
+    if train_rep:
+        out["surrogate_training"] = train_rep
     log(f"  {out['precision']}/{out['guess']}: {out['pair_evals_per_s']:.3e} pair-evals/s, "
         f"{out['ms_per_step']:.2f} ms/step, pair kernel {pair_ms:.2f} ms, {out['probes_per_pair']:.2f} probes/pair, "
         f"{out['achieved_tflops']:.1f} TFLOP/s algorithmic")
@@ -123,7 +149,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--paths", default="fp64:bisect,fp64:ballistic,mixed:bisect,mixed:ballistic")
+    ap.add_argument("--paths", default="fp64:bisect,mixed:mlp,mixed:bisect,mixed:ballistic,fp64:ballistic")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()

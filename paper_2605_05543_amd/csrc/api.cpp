@@ -43,7 +43,7 @@ hipError_t launch_mlp_sample(const SampleParams &p, const int64_t *tgt, const in
 hipError_t launch_mlp_group_guess(const MlpPacked *net, const GuessParams &p, float *G, hipStream_t s);
 hipError_t launch_group_centroid(const double4 *ring_w, const int32_t *order, int64_t N, int D, int head,
                                  double3 *centroid, hipStream_t s);
-hipError_t launch_group_centroid_x(const double *x, int64_t m, double3 *centroid, hipStream_t s);
+hipError_t launch_group_centroid_x(const double *x, int64_t m, int group, double3 *centroid, hipStream_t s);
 }  // namespace empp
 
 using namespace empp;
@@ -192,7 +192,7 @@ empp_status validate(const empp_config *c)
         return fail(EMPP_EINVAL, "unknown precision %d", c->precision);
     if (c->precision == EMPP_MIXED && !kHaveMixed)
         return fail(EMPP_EUNSUPPORTED, "mixed precision is not built");
-    if (c->guess < 0 || c->guess > 2)
+    if (c->guess < 0 || c->guess > 3)
         return fail(EMPP_EINVAL, "unknown guess mode %d", c->guess);
     return EMPP_OK;
 }
@@ -310,7 +310,7 @@ PairParams pair_params(empp_ctx *ctx)
     p.part = ctx->part();
     p.err = ctx->err();
     p.counters = ctx->counters();
-    p.guess = ctx->cfg.guess;
+    p.guess = ctx->cfg.guess == EMPP_GUESS_MLP_PAIR ? EMPP_GUESS_MLP : ctx->cfg.guess;
     p.dt = ctx->cfg.dt;
     return p;
 }
@@ -350,12 +350,33 @@ hipError_t timed(empp_ctx *ctx, int kind, F &&launch)
 // Surrogate guesses for a launch of m targets (external x or the
 // particles in spatial order): group centroids, then one network evaluation
 // per (group, source).
-hipError_t launch_guesses(empp_ctx *ctx, PairParams &p)
+hipError_t launch_guesses(empp_ctx *ctx, PairParams &p, float *G_pair = nullptr, double3 *cent_pair = nullptr)
 {
+    if (ctx->cfg.guess == EMPP_GUESS_MLP_PAIR) {
+        // one evaluation per (target, source): the "group" is the target
+        return timed(ctx, 2, [&]() {
+            hipError_t e = launch_group_centroid_x(p.x, p.m, 1, cent_pair, ctx->stream);
+            if (e != hipSuccess)
+                return e;
+            GuessParams gp{};
+            gp.ring_w = ctx->ring_w();
+            gp.ring_v = ctx->ring_v();
+            gp.T = ctx->T();
+            gp.centroid = cent_pair;
+            gp.N = ctx->cfg.n;
+            gp.ngroups = p.m;
+            gp.D = ctx->cfg.depth;
+            gp.head = ctx->head;
+            gp.inv_sigma = 1.0 / ctx->sg.sigma_ref;
+            p.G = G_pair;
+            p.g_shift = 0;
+            return launch_mlp_group_guess(ctx->sg.net, gp, G_pair, ctx->stream);
+        });
+    }
     if (ctx->cfg.guess != EMPP_GUESS_MLP)
         return hipSuccess;
     return timed(ctx, 2, [&]() {
-        hipError_t e = p.x ? launch_group_centroid_x(p.x, p.m, ctx->sg.cent, ctx->stream)
+        hipError_t e = p.x ? launch_group_centroid_x(p.x, p.m, 64, ctx->sg.cent, ctx->stream)
                            : launch_group_centroid(ctx->ring_w(), p.order, p.m, ctx->cfg.depth, ctx->head,
                                                    ctx->sg.cent, ctx->stream);
         if (e != hipSuccess)
@@ -376,9 +397,10 @@ hipError_t launch_guesses(empp_ctx *ctx, PairParams &p)
     });
 }
 
-hipError_t launch_pair(empp_ctx *ctx, PairParams &p, bool kstar)
+hipError_t launch_pair(empp_ctx *ctx, PairParams &p, bool kstar, float *G_pair = nullptr,
+                       double3 *cent_pair = nullptr)
 {
-    hipError_t eg = launch_guesses(ctx, p);
+    hipError_t eg = launch_guesses(ctx, p, G_pair, cent_pair);
     if (eg != hipSuccess)
         return eg;
     return timed(ctx, 0, [&]() {
@@ -593,6 +615,8 @@ empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
         return fail(EMPP_ESTATE, "step after handoff (use transport)");
     if (ctx->cfg.guess == EMPP_GUESS_MLP && !ctx->sg.ready)
         return fail(EMPP_ESTATE, "guess mode MLP without a surrogate network (empp_surrogate_set)");
+    if (ctx->cfg.guess == EMPP_GUESS_MLP_PAIR)
+        return fail(EMPP_EUNSUPPORTED, "per-pair surrogate guesses are available in fields_at only");
     empp_status st = set_device(ctx);
     if (st != EMPP_OK)
         return st;
@@ -656,7 +680,17 @@ static empp_status fields_dev_impl(empp_ctx *ctx, int64_t m, const double *x_dev
         p.self_index = self_dev ? self_dev + a0 : nullptr;
         p.m = mc;
         p.kstar = kstar_dev ? kstar_dev + a0 * N : nullptr;
-        hipError_t e = launch_pair(ctx, p, kstar_dev != nullptr);
+        float *G_pair = nullptr;
+        double3 *cent_pair = nullptr;
+        if (ctx->cfg.guess == EMPP_GUESS_MLP_PAIR) {
+            HIP_TRY(hipMalloc((void **)&G_pair, (size_t)mc * N * sizeof(float) + (size_t)mc * sizeof(double3) + 256));
+            cent_pair = (double3 *)((char *)G_pair + align_up((size_t)mc * N * sizeof(float)));
+        }
+        hipError_t e = launch_pair(ctx, p, kstar_dev != nullptr, G_pair, cent_pair);
+        if (G_pair) {
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipFree(G_pair);
+        }
         double *Ec = E_dev, *Bc = B_dev;
         double *tmpo = nullptr;
         if (e == hipSuccess && m > N) {
@@ -698,7 +732,7 @@ static empp_status fields_precheck(empp_ctx *ctx, double t, int64_t m)
         return fail(EMPP_EINVAL, "m < 0");
     if (t != ctx->t_now)
         return fail(EMPP_EINVAL, "t = %.17g is not the present time %.17g", t, ctx->t_now);
-    if (ctx->cfg.guess == EMPP_GUESS_MLP && !ctx->sg.ready)
+    if ((ctx->cfg.guess == EMPP_GUESS_MLP || ctx->cfg.guess == EMPP_GUESS_MLP_PAIR) && !ctx->sg.ready)
         return fail(EMPP_ESTATE, "guess mode MLP without a surrogate network (empp_surrogate_set)");
     return set_device(ctx);
 }

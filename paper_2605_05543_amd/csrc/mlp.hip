@@ -554,17 +554,18 @@ __global__ void group_centroid_kernel(const double4 *ring_w, const int32_t *orde
     centroid[grp] = make_double3(sx / cnt, sy / cnt, sz / cnt);
 }
 
-// Group centroids of external targets x[3][m] (64 consecutive per group).
-__global__ void group_centroid_x_kernel(const double *x, int64_t m, double3 *centroid)
+// Group centroids of external targets x[3][m] (`group` consecutive per
+// group; group 1 gives each target its own row).
+__global__ void group_centroid_x_kernel(const double *x, int64_t m, int group, double3 *centroid)
 {
     int64_t grp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t ngroups = (m + 63) / 64;
+    int64_t ngroups = (m + group - 1) / group;
     if (grp >= ngroups)
         return;
     double sx = 0, sy = 0, sz = 0;
     int cnt = 0;
-    for (int k = 0; k < 64; ++k) {
-        int64_t a = grp * 64 + k;
+    for (int k = 0; k < group; ++k) {
+        int64_t a = grp * group + k;
         if (a >= m)
             break;
         sx += x[a];
@@ -645,10 +646,11 @@ hipError_t launch_group_centroid(const double4 *ring_w, const int32_t *order, in
     return hipGetLastError();
 }
 
-hipError_t launch_group_centroid_x(const double *x, int64_t m, double3 *centroid, hipStream_t s)
+hipError_t launch_group_centroid_x(const double *x, int64_t m, int group, double3 *centroid, hipStream_t s)
 {
-    int64_t ng = (m + 63) / 64;
-    hipLaunchKernelGGL(group_centroid_x_kernel, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, x, m, centroid);
+    int64_t ng = (m + group - 1) / group;
+    hipLaunchKernelGGL(group_centroid_x_kernel, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, x, m, group,
+                       centroid);
     return hipGetLastError();
 }
 

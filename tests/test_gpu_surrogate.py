@@ -146,3 +146,47 @@ def test_guess_never_changes_results(precision):
         assert np.array_equal(k, ref[2]), name
         assert np.array_equal(E, ref[0]) and np.array_equal(B, ref[1]), name
     assert outs["garbage"][3]["fallbacks"] > 0
+
+
+def test_what_the_network_gains():
+    """C3 workload (N=65536, D=512, dipole): the network trained on pairs from
+    C2 and C3 bunches against the method without it.  Iterations (sign
+    tests per pair) over 1024 seeded targets x all sources for the paper's
+    bisection, the network evaluated per pair, the network amortised over
+    groups of 64 targets, and the closed-form ballistic guess; k* and fields
+    are identical in all four."""
+    from paper_2605_05543_amd import surrogate
+    from paper_2605_05543_amd._lib import EMPP_GUESS_BALLISTIC, EMPP_GUESS_BISECT, EMPP_GUESS_MLP, EMPP_GUESS_MLP_PAIR
+
+    print("case surrogate gain on C3", flush=True)
+    wl = bunch.C3
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    n = wl.bunch.n
+    sX2, sy2 = surrogate.draw_samples(bunch.C2, 1 << 21, seed=21)
+    with _ctx(n, wl.depth, wl.dt) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        ctx.step(4)
+        ctx.surrogate_set(bunch.surrogate_init(0), bunch.sigma_ref_of(r))
+        sX3, sy3 = ctx.surrogate_samples_torch(1 << 21, seed=23)
+        rep = surrogate.train(ctx, [(sX2, sy2), (sX3, sy3)], batch=8192, steps=1536)
+        print(f"   training: loss {rep['loss_first']:.3e} -> {rep['loss_last']:.3e}, {rep['steps']} steps, "
+              f"{rep['seconds']:.2f} s", flush=True)
+        sub = bunch.target_subset(n, 1024, 103)
+        rg, _, t, _ = ctx.state()
+        x = rg[:, sub]
+        out = {}
+        for name, g in (("bisect", EMPP_GUESS_BISECT), ("mlp-pair", EMPP_GUESS_MLP_PAIR),
+                        ("mlp-group", EMPP_GUESS_MLP), ("ballistic", EMPP_GUESS_BALLISTIC)):
+            ctx.set_mode(0, g)
+            ctx.set_counting(True)
+            E, B, k = ctx.fields_at(t, x, sub, want_kstar=True)
+            c = ctx.counters()
+            out[name] = (E, B, k, c["probes"] / c["pairs"], c["fallbacks"] / c["pairs"])
+            print(f"   {name}: {out[name][3]:.2f} sign tests per pair, fallbacks per pair {out[name][4]:.2e}",
+                  flush=True)
+    for name in out:
+        assert np.array_equal(out[name][2], out["bisect"][2]), name
+        assert np.array_equal(out[name][0], out["bisect"][0]) and np.array_equal(out[name][1], out["bisect"][1])
+    assert rep["loss_last"] < 0.05 * rep["loss_first"]
+    assert out["mlp-pair"][3] < out["bisect"][3]
