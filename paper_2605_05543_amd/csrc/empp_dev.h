@@ -92,17 +92,14 @@ __device__ inline void report_error(unsigned long long *err, int64_t a, int64_t 
     atomicOr(&err[1], bit);
 }
 
-// Reciprocal of a positive normal double: hardware estimate plus two
-// Newton-Raphson steps (the estimate is good to ~2^-29, each step squares
-// the relative error), accurate to about one unit in the last place.
+// Reciprocal of a positive normal double: hardware estimate plus one
+// Newton-Raphson step, which squares the estimate's relative error (about
+// 2^-26) to the last bits of the mantissa.
 __device__ inline double rcp64(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
     double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    return r;
+    return __builtin_fma(r, e, r);
 }
 
 // Neumaier accumulation of x into (s, c).

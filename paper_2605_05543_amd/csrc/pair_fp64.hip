@@ -11,7 +11,7 @@
 // velocity records are fetched together and the S pair fields evaluated.
 // Targets are visited in a spatial (Morton) order so that the lanes of a
 // wavefront probe nearby history slots.  Sums are kept per target in
-// registers: a plain partial per tile merged into a Neumaier-compensated
+// registers: a plain partial over 8 tiles merged into a Neumaier-compensated
 // total; source chunks (grid.y) write (sum, compensation) partials that the
 // push kernel merges in a fixed order, so results do not depend on
 // scheduling.
@@ -124,6 +124,8 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
         }
     }
     double sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    int tiles_in_acc = 0;
     int probes = 0, nbefore = 0, npairs = 0, nfall = 0;
     bool failed = false;
     int64_t fail_j = 0;
@@ -136,21 +138,56 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
         ph += ph < 0 ? D : 0;
         Ls[b] = kC_LIGHT * (p.t - p.T[ph]);
     }
+    // Tile records are prefetched into registers one tile ahead (the first
+    // two records of each thread), so their HBM/L2 latency overlaps the
+    // previous tile's work; deeper histories load the rest in place.
+    // Record q of a tile: source q / D (q < S D, S <= 2), slot q % D.
+    auto fetch = [&](int64_t jt, int ns, int q) -> double4 {
+        int s = S == 2 && q >= D ? 1 : 0;
+        int b = q - s * D;
+        double4 w = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (b < D && s < ns) {
+            int ph = p.head - b;
+            ph += ph < 0 ? D : 0;
+            w = p.ring_w[(jt + s) * D + ph];
+        }
+        return w;
+    };
+    auto put = [&](int ns, int q, double4 w) {
+        int s = S == 2 && q >= D ? 1 : 0;
+        int b = q - s * D;
+        if (b < D && s < ns) {
+            double L = Ls[b];
+            w.w = L * L;
+            lds[s * D + b] = w;
+        }
+    };
+    double4 pf0 = make_double4(0.0, 0.0, 0.0, 0.0), pf1 = pf0;
+    if (j0 < j1) {
+        const int ns0 = (int)((j1 - j0) < S ? (j1 - j0) : S);
+        pf0 = fetch(j0, ns0, tid);
+        pf1 = fetch(j0, ns0, tid + kBlock);
+    }
     for (int64_t jt = j0; jt < j1; jt += S) {
         const int ns = (int)((j1 - jt) < S ? (j1 - jt) : S);
         __syncthreads();
-        for (int s = 0; s < ns; ++s) {
-            const double4 *src = p.ring_w + (jt + s) * D;
-            for (int b = tid; b < D; b += kBlock) {
-                int ph = p.head - b;
-                ph += ph < 0 ? D : 0;
-                double4 w = src[ph];
-                double L = Ls[b];
-                w.w = L * L;
-                lds[s * D + b] = w;
-            }
+        put(ns, tid, pf0);
+        put(ns, tid + kBlock, pf1);
+        for (int q = tid + 2 * kBlock; q < ns * D; q += kBlock) {
+            int s = q / D, b = q - (q / D) * D;
+            int ph = p.head - b;
+            ph += ph < 0 ? D : 0;
+            double4 w = p.ring_w[(jt + s) * D + ph];
+            double L = Ls[b];
+            w.w = L * L;
+            lds[s * D + b] = w;
         }
         __syncthreads();
+        if (jt + S < j1) {
+            const int nsn = (int)((j1 - jt - S) < S ? (j1 - jt - S) : S);
+            pf0 = fetch(jt + S, nsn, tid);
+            pf1 = fetch(jt + S, nsn, tid + kBlock);
+        }
         if (!active)
             continue;
 
@@ -172,6 +209,40 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
                 valid[s] = false;
             }
         }
+
+        // bracket velocity records (they carry 1/(t_2 - t_1)), root,
+        // reconstruction, LW field and accumulation of tile source s
+        auto load_v = [&](int s, int b, double4 &v1, double4 &v2) {
+            const int bb = b < 0 ? D - 1 : b;
+            int ph1 = p.head - bb;
+            ph1 += ph1 < 0 ? D : 0;
+            int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
+            v1 = p.ring_v[jj[s] * D + ph1];
+            v2 = p.ring_v[jj[s] * D + ph2];  // unused (inv_h = 0) out of history
+        };
+        auto finish = [&](int s, int b, double4 v1, double4 v2) {
+            const bool before = b < 0;
+            const int bb = before ? D - 1 : b;
+            double f[6];
+            bool ok = lw_pair(rx, ry, rz, lds[s * D + bb], Ls[bb], v1, v2, before, p.kq, f);
+            if (valid[s]) {
+                if (ok) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        acc[k] += f[k];
+                } else {
+                    if (!failed)
+                        fail_j = jj[s];
+                    failed = true;
+                }
+                if (KSTAR)
+                    p.kstar[a * p.n_src + jj[s]] = before ? -1 : b;
+                if (COUNT) {
+                    npairs += 1;
+                    nbefore += before ? 1 : 0;
+                }
+            }
+        };
 
         if (GUESS == 0) {
             // The paper's search: oldest sample first, then bisection of the
@@ -208,72 +279,55 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
                 if (COUNT && valid[s])
                     probes += inside[s] ? 1 + p.nit : 1;
             }
+            double4 v1[S], v2[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                load_v(s, bk[s], v1[s], v2[s]);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                finish(s, bk[s], v1[s], v2[s]);
         } else {
+            // guided searches, one source at a time
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                bk[s] = -1;
-                if (!valid[s])
-                    continue;
-                const double4 *rec = lds + s * D;
-                auto test = [&](int b) { return lightcone_positive(rec[b], rx, ry, rz); };
-                double4 wn = rec[0];
-                float g;
-                if (GUESS == 2) {
-                    double4 vn = p.ring_v[jj[s] * D + p.head];
-                    g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
-                } else {
-                    // surrogate: predicted c (t - t_r) / |r - w_n| times this target's distance
-                    float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
-                    float gh = p.G[(a >> p.g_shift) * p.n_src + jj[s]];
-                    g = gh * __builtin_amdgcn_sqrtf(Rx * Rx + Ry * Ry + Rz * Rz) * inv_cdt;
+                int b = -1;
+                if (valid[s]) {
+                    const double4 *rec = lds + s * D;
+                    auto test = [&](int bb) { return lightcone_positive(rec[bb], rx, ry, rz); };
+                    double4 wn = rec[0];
+                    float g;
+                    if (GUESS == 2) {
+                        double4 vn = p.ring_v[jj[s] * D + p.head];
+                        g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
+                    } else {
+                        // surrogate: predicted c (t - t_r) / |r - w_n| times this target's distance
+                        float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
+                        float gh = p.G[(a >> p.g_shift) * p.n_src + jj[s]];
+                        g = gh * __builtin_amdgcn_sqrtf(Rx * Rx + Ry * Ry + Rz * Rz) * inv_cdt;
+                    }
+                    int fb = 0;
+                    b = search_guided(test, D, g, 6, probes, fb);
+                    nfall += fb;
                 }
-                int fb = 0;
-                bk[s] = search_guided(test, D, g, 6, probes, fb);
-                nfall += fb;
+                double4 v1, v2;
+                load_v(s, b, v1, v2);
+                finish(s, b, v1, v2);
             }
         }
-
-        // bracket velocity records (they carry their slot times)
-        double4 v1[S], v2[S];
+        // plain partial sums over 8 tiles, then one compensated merge (the
+        // same cadence for every search mode: results are bit-identical)
+        if (++tiles_in_acc == 8) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const bool before = bk[s] < 0;
-            const int bb = before ? D - 1 : bk[s];
-            int ph1 = p.head - bb;
-            ph1 += ph1 < 0 ? D : 0;
-            int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
-            v1[s] = p.ring_v[jj[s] * D + ph1];
-            v2[s] = p.ring_v[jj[s] * D + ph2];  // unused (inv_h = 0) out of history
-        }
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const bool before = bk[s] < 0;
-            const int bb = before ? D - 1 : bk[s];
-            double f[6];
-            bool ok = lw_pair(rx, ry, rz, lds[s * D + bb], Ls[bb], v1[s], v2[s], before, p.kq, f);
-            if (valid[s]) {
-                if (ok) {
-#pragma unroll
-                    for (int k = 0; k < 6; ++k)
-                        acc[k] += f[k];
-                } else {
-                    if (!failed)
-                        fail_j = jj[s];
-                    failed = true;
-                }
-                if (KSTAR)
-                    p.kstar[a * p.n_src + jj[s]] = before ? -1 : bk[s];
-                if (COUNT) {
-                    npairs += 1;
-                    nbefore += before ? 1 : 0;
-                }
+            for (int k = 0; k < 6; ++k) {
+                neumaier(sum[k], comp[k], acc[k]);
+                acc[k] = 0.0;
             }
+            tiles_in_acc = 0;
         }
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-            neumaier(sum[k], comp[k], acc[k]);
     }
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        neumaier(sum[k], comp[k], acc[k]);
     if (active) {
         double *out = p.part + (int64_t)split * 12 * p.m + tgt;
         for (int k = 0; k < 6; ++k) {
