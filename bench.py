@@ -38,6 +38,27 @@ FLOP_INRING = 32 + 20 + 69 + 6
 FLOP_BEFORE = 32 + 6 + 48 + 6
 
 
+def measured_traffic():
+    """HBM bytes per launch of the FP64 pair kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
+    has changed since those counters were taken."""
+    import hashlib
+    import re
+
+    prof = os.path.join(ROOT, "profiles", "pair_fp64_c3_traffic.md")
+    src = os.path.join(ROOT, "paper_2605_05543_amd", "csrc", "pair_fp64.hip")
+    try:
+        text = open(prof).read()
+    except OSError:
+        return None
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m_h = re.search(r"source: pair_fp64.hip sha256 ([0-9a-f]+)", text)
+    if not (m_b and m_h):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return float(m_b.group(1)) if sha.startswith(m_h.group(1)) else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -203,7 +224,8 @@ def main():
         "config": {"workload": wl.name, "n": n, "depth": wl.depth, "dt": wl.dt, "ext_field": wl.ext_field,
                    "precision": head["precision"], "search": head["guess"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                     "traffic": measured_traffic() if wl is bunch.C3 else None,
                      "kernel": "pair_fp64_kernel (plain FP64 path)",
                      "flops_per_pair": plain["flops_per_pair"], "launch_ms": plain["pair_kernel_ms"]},
         "paths": results,
