@@ -185,8 +185,8 @@ def main():
         log("copied 3 x 1 GiB")
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the pair sum would shard by "
-              "targets with a replicated history; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the pair sum would shard by "
+              "targets, each GPU holding a replica of the history ring). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     wl = {"c1": bunch.C1, "c2": bunch.C2, "c3": bunch.C3, "c5": bunch.C5}[args.workload]
     import torch

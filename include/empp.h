@@ -60,7 +60,7 @@ typedef enum {
     EMPP_EDEVICE = 3,      /* HIP runtime error (message has its text)     */
     EMPP_ESTATE = 4,       /* call not valid in the context's state        */
     EMPP_ENUMERIC = 5,     /* coincident particles or negative discriminant */
-    EMPP_EUNSUPPORTED = 6  /* option not available in this build           */
+    EMPP_EUNSUPPORTED = 6  /* option not available in this library         */
 } empp_status;
 
 typedef enum {

@@ -15,7 +15,8 @@ SOURCES = ["api.cpp", "pair_fp64.hip", "pair_mixed.hip", "push.hip", "mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed FP32 instructions stay off ("Toolchain")
+    # packed FP32 instructions (v_pk_*_f32) stay off; the compiler emits
+    # scalar FP32 instead
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]

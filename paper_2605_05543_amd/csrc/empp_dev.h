@@ -46,6 +46,7 @@ struct PairParams {
     int64_t src_per_split;
     int32_t nsplit;
     int32_t tile;               // sources staged per LDS tile
+    int32_t nbuf;               // LDS tile buffers (FP64 kernel: 1 or 2)
     double *part;               // [nsplit][12][m] partial (sum, comp)
     int32_t *kstar;             // [m][N] or null
     unsigned long long *err;    // [2]: first failing pair, status bits

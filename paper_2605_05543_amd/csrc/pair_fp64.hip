@@ -1,11 +1,11 @@
 // pair_fp64.hip -- all-pairs Lienard-Wiechert field evaluation in double
 // precision (Secs. 2.1-2.2 of arXiv 2605.05543).
 //
-// One thread owns one target.  A block of 256 targets walks its chunk of
-// sources in tiles of S sources: the tile's histories (positions plus the
-// light distance c (t - T_k) of every slot) are staged once into LDS and
-// every target of the block then searches them, so each history byte read
-// from L2/HBM serves 256 targets.  The S searches of a tile run in
+// One thread owns one target.  A block of kBlock (512) targets walks its
+// chunk of sources in tiles of S sources: the tile's histories (positions
+// plus the light distance c (t - T_k) of every slot) are staged once into
+// LDS and every target of the block then searches them, so each history
+// byte read from L2/HBM serves 512 targets.  The S searches of a tile run in
 // lockstep (a fixed number of bisection steps, no divergence), so S
 // independent LDS chains are in flight per lane; then the 2 S bracket
 // velocity records are fetched together and the S pair fields evaluated.
@@ -131,8 +131,10 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
     int64_t fail_j = 0;
     const float inv_cdt = (float)(1.0 / (kC_LIGHT * p.dt));
 
-    // light distance of every logical slot, shared by all sources
-    double *Ls = reinterpret_cast<double *>(lds + S * D);
+    // LDS: nbuf tile buffers of S * D records, then the light distance of
+    // every logical slot (shared by all sources).
+    const int nbuf = p.nbuf;
+    double *Ls = reinterpret_cast<double *>(lds + nbuf * S * D);
     for (int b = tid; b < D; b += kBlock) {
         int ph = p.head - b;
         ph += ph < 0 ? D : 0;
@@ -153,26 +155,18 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
         }
         return w;
     };
-    auto put = [&](int ns, int q, double4 w) {
+    auto put = [&](double4 *buf, int ns, int q, double4 w) {
         int s = S == 2 && q >= D ? 1 : 0;
         int b = q - s * D;
         if (b < D && s < ns) {
             double L = Ls[b];
             w.w = L * L;
-            lds[s * D + b] = w;
+            buf[s * D + b] = w;
         }
     };
-    double4 pf0 = make_double4(0.0, 0.0, 0.0, 0.0), pf1 = pf0;
-    if (j0 < j1) {
-        const int ns0 = (int)((j1 - j0) < S ? (j1 - j0) : S);
-        pf0 = fetch(j0, ns0, tid);
-        pf1 = fetch(j0, ns0, tid + kBlock);
-    }
-    for (int64_t jt = j0; jt < j1; jt += S) {
-        const int ns = (int)((j1 - jt) < S ? (j1 - jt) : S);
-        __syncthreads();
-        put(ns, tid, pf0);
-        put(ns, tid + kBlock, pf1);
+    auto stage = [&](double4 *buf, int64_t jt, int ns, double4 r0, double4 r1) {
+        put(buf, ns, tid, r0);
+        put(buf, ns, tid + kBlock, r1);
         for (int q = tid + 2 * kBlock; q < ns * D; q += kBlock) {
             int s = q / D, b = q - (q / D) * D;
             int ph = p.head - b;
@@ -180,138 +174,173 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
             double4 w = p.ring_w[(jt + s) * D + ph];
             double L = Ls[b];
             w.w = L * L;
-            lds[s * D + b] = w;
+            buf[s * D + b] = w;
+        }
+    };
+    auto tile_size = [&](int64_t jt) { return (int)((j1 - jt) < S ? (j1 - jt) : S); };
+    double4 pf0 = make_double4(0.0, 0.0, 0.0, 0.0), pf1 = pf0;
+    if (j0 < j1) {
+        pf0 = fetch(j0, tile_size(j0), tid);
+        pf1 = fetch(j0, tile_size(j0), tid + kBlock);
+    }
+    // Two buffers: tile i + 1 is written while tile i is searched, and one
+    // barrier per tile both publishes tile i + 1 and retires tile i's
+    // buffer for tile i + 2.  One buffer (deep histories): stage, then
+    // search, with a barrier on either side.
+    if (nbuf == 2 && j0 < j1) {
+        __syncthreads();
+        stage(lds, j0, tile_size(j0), pf0, pf1);
+        if (j0 + S < j1) {
+            pf0 = fetch(j0 + S, tile_size(j0 + S), tid);
+            pf1 = fetch(j0 + S, tile_size(j0 + S), tid + kBlock);
         }
         __syncthreads();
-        if (jt + S < j1) {
-            const int nsn = (int)((j1 - jt - S) < S ? (j1 - jt - S) : S);
-            pf0 = fetch(jt + S, nsn, tid);
-            pf1 = fetch(jt + S, nsn, tid + kBlock);
-        }
-        if (!active)
-            continue;
-
-        bool valid[S];
-        int64_t jj[S];
-        int bk[S];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            jj[s] = jt + (s < ns ? s : 0);
-            valid[s] = s < ns && jj[s] != self;
-            if (KSTAR && s < ns && jj[s] == self)
-                p.kstar[a * p.n_src + jj[s]] = 0;
-            // a target on the source's present position: eta = 0
-            double4 wn = lds[s * D];
-            if (valid[s] && rx == wn.x && ry == wn.y && rz == wn.z) {
-                if (!failed)
-                    fail_j = jj[s];
-                failed = true;
-                valid[s] = false;
+    }
+    int it = 0;
+    for (int64_t jt = j0; jt < j1; jt += S, ++it) {
+        const int ns = tile_size(jt);
+        double4 *cur = lds;
+        if (nbuf == 2) {
+            cur = lds + (it & 1) * (S * D);
+            if (jt + S < j1) {
+                stage(lds + ((it + 1) & 1) * (S * D), jt + S, tile_size(jt + S), pf0, pf1);
+                if (jt + 2 * S < j1) {
+                    pf0 = fetch(jt + 2 * S, tile_size(jt + 2 * S), tid);
+                    pf1 = fetch(jt + 2 * S, tile_size(jt + 2 * S), tid + kBlock);
+                }
+            }
+        } else {
+            __syncthreads();
+            stage(lds, jt, ns, pf0, pf1);
+            __syncthreads();
+            if (jt + S < j1) {
+                pf0 = fetch(jt + S, tile_size(jt + S), tid);
+                pf1 = fetch(jt + S, tile_size(jt + S), tid + kBlock);
             }
         }
-
-        // bracket velocity records (they carry 1/(t_2 - t_1)), root,
-        // reconstruction, LW field and accumulation of tile source s
-        auto load_v = [&](int s, int b, double4 &v1, double4 &v2) {
-            const int bb = b < 0 ? D - 1 : b;
-            int ph1 = p.head - bb;
-            ph1 += ph1 < 0 ? D : 0;
-            int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
-            v1 = p.ring_v[jj[s] * D + ph1];
-            v2 = p.ring_v[jj[s] * D + ph2];  // unused (inv_h = 0) out of history
-        };
-        auto finish = [&](int s, int b, double4 v1, double4 v2) {
-            const bool before = b < 0;
-            const int bb = before ? D - 1 : b;
-            double f[6];
-            bool ok = lw_pair(rx, ry, rz, lds[s * D + bb], Ls[bb], v1, v2, before, p.kq, f);
-            if (valid[s]) {
-                if (ok) {
-#pragma unroll
-                    for (int k = 0; k < 6; ++k)
-                        acc[k] += f[k];
-                } else {
+        if (active) {
+            bool valid[S];
+            int64_t jj[S];
+            int bk[S];
+    #pragma unroll
+            for (int s = 0; s < S; ++s) {
+                jj[s] = jt + (s < ns ? s : 0);
+                valid[s] = s < ns && jj[s] != self;
+                if (KSTAR && s < ns && jj[s] == self)
+                    p.kstar[a * p.n_src + jj[s]] = 0;
+                // a target on the source's present position: eta = 0
+                double4 wn = cur[s * D];
+                if (valid[s] && rx == wn.x && ry == wn.y && rz == wn.z) {
                     if (!failed)
                         fail_j = jj[s];
                     failed = true;
-                }
-                if (KSTAR)
-                    p.kstar[a * p.n_src + jj[s]] = before ? -1 : b;
-                if (COUNT) {
-                    npairs += 1;
-                    nbefore += before ? 1 : 0;
+                    valid[s] = false;
                 }
             }
-        };
 
-        if (GUESS == 0) {
-            // The paper's search: oldest sample first, then bisection of the
-            // whole history; a fixed number of halvings keeps the S searches
-            // in lockstep (extra halvings of a one-step bracket change
-            // nothing).
-            bool inside[S];
-            int xb[S];  // f(xb) <= 0; the bracket lies in (xb, xb + n]
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                inside[s] = lightcone_positive(lds[s * D + D - 1], rx, ry, rz);
-                xb[s] = 0;
-            }
-            bool any = false;
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-                any = any || (inside[s] && valid[s]);
-            if (__any(any)) {
-                // halving widths depend on D only: uniform across lanes
-                for (int n = D - 1; n > 1;) {
-                    const int half = n >> 1;
-#pragma unroll
-                    for (int s = 0; s < S; ++s) {
-                        int m = xb[s] + half;
-                        bool f = lightcone_positive(lds[s * D + m], rx, ry, rz);
-                        xb[s] = f ? xb[s] : m;
-                    }
-                    n -= half;
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                bk[s] = inside[s] ? xb[s] + 1 : -1;
-                if (COUNT && valid[s])
-                    probes += inside[s] ? 1 + p.nit : 1;
-            }
-            double4 v1[S], v2[S];
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-                load_v(s, bk[s], v1[s], v2[s]);
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-                finish(s, bk[s], v1[s], v2[s]);
-        } else {
-            // guided searches, one source at a time
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                int b = -1;
+            // bracket velocity records (they carry 1/(t_2 - t_1)), root,
+            // reconstruction, LW field and accumulation of tile source s
+            auto load_v = [&](int s, int b, double4 &v1, double4 &v2) {
+                const int bb = b < 0 ? D - 1 : b;
+                int ph1 = p.head - bb;
+                ph1 += ph1 < 0 ? D : 0;
+                int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
+                v1 = p.ring_v[jj[s] * D + ph1];
+                v2 = p.ring_v[jj[s] * D + ph2];  // unused (inv_h = 0) out of history
+            };
+            auto finish = [&](int s, int b, double4 v1, double4 v2) {
+                const bool before = b < 0;
+                const int bb = before ? D - 1 : b;
+                double f[6];
+                bool ok = lw_pair(rx, ry, rz, cur[s * D + bb], Ls[bb], v1, v2, before, p.kq, f);
                 if (valid[s]) {
-                    const double4 *rec = lds + s * D;
-                    auto test = [&](int bb) { return lightcone_positive(rec[bb], rx, ry, rz); };
-                    double4 wn = rec[0];
-                    float g;
-                    if (GUESS == 2) {
-                        double4 vn = p.ring_v[jj[s] * D + p.head];
-                        g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
+                    if (ok) {
+    #pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            acc[k] += f[k];
                     } else {
-                        // surrogate: predicted c (t - t_r) / |r - w_n| times this target's distance
-                        float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
-                        float gh = p.G[(a >> p.g_shift) * p.n_src + jj[s]];
-                        g = gh * __builtin_amdgcn_sqrtf(Rx * Rx + Ry * Ry + Rz * Rz) * inv_cdt;
+                        if (!failed)
+                            fail_j = jj[s];
+                        failed = true;
                     }
-                    int fb = 0;
-                    b = search_guided(test, D, g, 6, probes, fb);
-                    nfall += fb;
+                    if (KSTAR)
+                        p.kstar[a * p.n_src + jj[s]] = before ? -1 : b;
+                    if (COUNT) {
+                        npairs += 1;
+                        nbefore += before ? 1 : 0;
+                    }
                 }
-                double4 v1, v2;
-                load_v(s, b, v1, v2);
-                finish(s, b, v1, v2);
+            };
+
+            if (GUESS == 0) {
+                // The paper's search: oldest sample first, then bisection of the
+                // whole history; a fixed number of halvings keeps the S searches
+                // in lockstep (extra halvings of a one-step bracket change
+                // nothing).
+                bool inside[S];
+                int xb[S];  // f(xb) <= 0; the bracket lies in (xb, xb + n]
+    #pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    inside[s] = lightcone_positive(cur[s * D + D - 1], rx, ry, rz);
+                    xb[s] = 0;
+                }
+                bool any = false;
+    #pragma unroll
+                for (int s = 0; s < S; ++s)
+                    any = any || (inside[s] && valid[s]);
+                if (__any(any)) {
+                    // halving widths depend on D only: uniform across lanes
+                    for (int n = D - 1; n > 1;) {
+                        const int half = n >> 1;
+    #pragma unroll
+                        for (int s = 0; s < S; ++s) {
+                            int m = xb[s] + half;
+                            bool f = lightcone_positive(cur[s * D + m], rx, ry, rz);
+                            xb[s] = f ? xb[s] : m;
+                        }
+                        n -= half;
+                    }
+                }
+    #pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    bk[s] = inside[s] ? xb[s] + 1 : -1;
+                    if (COUNT && valid[s])
+                        probes += inside[s] ? 1 + p.nit : 1;
+                }
+                double4 v1[S], v2[S];
+    #pragma unroll
+                for (int s = 0; s < S; ++s)
+                    load_v(s, bk[s], v1[s], v2[s]);
+    #pragma unroll
+                for (int s = 0; s < S; ++s)
+                    finish(s, bk[s], v1[s], v2[s]);
+            } else {
+                // guided searches, one source at a time
+    #pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    int b = -1;
+                    if (valid[s]) {
+                        const double4 *rec = cur + s * D;
+                        auto test = [&](int bb) { return lightcone_positive(rec[bb], rx, ry, rz); };
+                        double4 wn = rec[0];
+                        float g;
+                        if (GUESS == 2) {
+                            double4 vn = p.ring_v[jj[s] * D + p.head];
+                            g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
+                        } else {
+                            // surrogate: predicted c (t - t_r) / |r - w_n| times this target's distance
+                            float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
+                            float gh = p.G[(a >> p.g_shift) * p.n_src + jj[s]];
+                            g = gh * __builtin_amdgcn_sqrtf(Rx * Rx + Ry * Ry + Rz * Rz) * inv_cdt;
+                        }
+                        int fb = 0;
+                        b = search_guided(test, D, g, 6, probes, fb);
+                        nfall += fb;
+                    }
+                    double4 v1, v2;
+                    load_v(s, b, v1, v2);
+                    finish(s, b, v1, v2);
+                }
             }
         }
         // plain partial sums over 8 tiles, then one compensated merge (the
@@ -324,6 +353,8 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
             }
             tiles_in_acc = 0;
         }
+        if (nbuf == 2)
+            __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k)
@@ -356,15 +387,26 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
 }
 
 // Sources per LDS tile for a history depth: two when two histories fit in
-// 64 KiB, else one (depths up to 4096 use up to 136 KiB with the slot
+// 64 KiB, else one (depths up to 4096 use up to 160 KiB with the slot
 // light distances).
 int pair_fp64_tile(int D) { return D <= 1024 ? 2 : 1; }
 
-// Host-side launcher (called from the C ABI layer).
-hipError_t launch_pair_fp64(const PairParams &p, hipStream_t stream, bool kstar, bool count)
+// LDS buffers: two (staging overlapped with the search) while two tiles
+// and the light distances fit in 80 KiB, so that two 512-thread blocks
+// share a CU; else one.
+int pair_fp64_nbuf(int D, int tile)
 {
+    size_t two = 2 * (size_t)tile * D * sizeof(double4) + (size_t)D * sizeof(double);
+    return two <= 80 * 1024 ? 2 : 1;
+}
+
+// Host-side launcher (called from the C ABI layer).
+hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar, bool count)
+{
+    PairParams p = p0;
+    p.nbuf = pair_fp64_nbuf(p.D, p.tile);
     dim3 grid((unsigned)((p.m + kBlock - 1) / kBlock), (unsigned)p.nsplit);
-    size_t lds = (size_t)p.tile * p.D * sizeof(double4) + (size_t)p.D * sizeof(double);
+    size_t lds = (size_t)p.nbuf * p.tile * p.D * sizeof(double4) + (size_t)p.D * sizeof(double);
 #define EMPP_LAUNCH(K, C, G, S)                                                                              \
     do {                                                                                                    \
         if (lds > 65536)                                                                                    \
