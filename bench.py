@@ -34,6 +34,7 @@ PEAK_HBM_GBS = 8000.0
 #   LW E and B, Eqs. (LW_E), (LW_B):               69 / 48 (a = 0 out of history)
 #   accumulation of E and B:                        6
 FLOP_PROBE = 9
+GUESS_NAMES = ["bisect", "mlp", "ballistic", None, "previous"]
 FLOP_INRING = 32 + 20 + 69 + 6
 FLOP_BEFORE = 32 + 6 + 48 + 6
 
@@ -95,11 +96,14 @@ def run_path(wl, r, u, precision, guess, steps, warmup):
 
     n = wl.bunch.n
     ctx = Context(n=n, depth=wl.depth, q=-bunch.E_CHARGE, m=bunch.M_ELECTRON, dt=wl.dt, ext_field=wl.ext_field,
-                  dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re, precision=precision, guess=0)
+                  dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re, precision=precision,
+                  guess=4 if guess == 4 else 0)
     ctx.init_bunch(r, u, 0.0)
     ctx.init_history_straight()
     train_rep = train_surrogate(ctx, wl, r) if guess == 1 else None
     ctx.set_mode(precision, guess)
+    if guess == 4:
+        ctx.step(1)  # the first step bisects and fills the bracket cache
     # one counting step (untimed) for the algorithmic work per launch
     ctx.set_counting(True)
     ctx.step(1)
@@ -123,7 +127,7 @@ def run_path(wl, r, u, precision, guess, steps, warmup):
     pair_ms = tim["pair_ms"] / max(1, tim["pair_launches"])
     flops = algorithmic_flops(cnt)
     out = {
-        "precision": ["fp64", "mixed"][precision], "guess": ["bisect", "mlp", "ballistic"][guess],
+        "precision": ["fp64", "mixed"][precision], "guess": GUESS_NAMES[guess],
         "pair_evals_per_s": pairs * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
         "pair_kernel_ms": pair_ms, "push_kernel_ms": tim["push_ms"] / max(1, tim["push_launches"]),
         "probes_per_pair": cnt["probes"] / cnt["pairs"], "before_history_fraction": cnt["before"] / cnt["pairs"],
@@ -170,7 +174,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--paths", default="fp64:bisect,mixed:mlp,mixed:bisect,mixed:ballistic,fp64:ballistic")
+    ap.add_argument("--paths", default="fp64:bisect,mixed:mlp,mixed:bisect,mixed:ballistic,fp64:ballistic,"
+                                        "fp64:previous")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -195,7 +200,7 @@ def main():
     r, u = bunch.gaussian_bunch(wl.bunch)
     log(f"workload {wl.name}: N={wl.bunch.n} D={wl.depth} dt={wl.dt} steps={args.steps} warmup={args.warmup}")
     pmap = {"fp64": 0, "mixed": 1}
-    gmap = {"bisect": 0, "mlp": 1, "ballistic": 2}
+    gmap = {name: k for k, name in enumerate(GUESS_NAMES) if name}
     results = []
     for spec in args.paths.split(","):
         p, g = spec.split(":")

@@ -76,9 +76,16 @@ typedef enum {
     EMPP_GUESS_MLP = 1,       /* start from the surrogate network's delay  */
     EMPP_GUESS_BALLISTIC = 2, /* start from the closed-form delay of a source
                                  coasting with its newest velocity          */
-    EMPP_GUESS_MLP_PAIR = 3   /* surrogate evaluated for every pair (fields_at
+    EMPP_GUESS_MLP_PAIR = 3,  /* surrogate evaluated for every pair (fields_at
                                  only: measures the network's own accuracy
                                  at one evaluation per pair)                */
+    EMPP_GUESS_PREVIOUS = 4   /* start from the pair's bracket of the previous
+                                 step (FP64 path, empp_step only; fields_at
+                                 bisects).  The workspace then holds N*N
+                                 uint16 brackets (8 GiB at N = 65536); the
+                                 first step after a history is set bisects.
+                                 Set at creation: empp_set_mode cannot
+                                 switch a context without the cache to it. */
 } empp_guess;
 
 typedef struct {

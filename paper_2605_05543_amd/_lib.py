@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libempp.so")
 EMPP_OK, EMPP_EINVAL, EMPP_ENOMEM, EMPP_EDEVICE, EMPP_ESTATE, EMPP_ENUMERIC, EMPP_EUNSUPPORTED = range(7)
 STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "ESTATE", "ENUMERIC", "EUNSUPPORTED"]
 EMPP_FP64, EMPP_MIXED = 0, 1
-EMPP_GUESS_BISECT, EMPP_GUESS_MLP, EMPP_GUESS_BALLISTIC, EMPP_GUESS_MLP_PAIR = 0, 1, 2, 3
+EMPP_GUESS_BISECT, EMPP_GUESS_MLP, EMPP_GUESS_BALLISTIC, EMPP_GUESS_MLP_PAIR, EMPP_GUESS_PREVIOUS = 0, 1, 2, 3, 4
 
 # Functions declared in include/empp.h (tests check that each is exported).
 EXPORTS = [

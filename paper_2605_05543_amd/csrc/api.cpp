@@ -79,7 +79,7 @@ constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, order, total;
+    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, order, kc, kc_bytes, total;
 };
 
 int tile_for_depth(int D) { return pair_fp64_tile(D); }
@@ -166,6 +166,9 @@ Layout layout_for(const empp_config &c)
     L.counters = take(8 * sizeof(unsigned long long));
     L.diag = take(((N + kBlock - 1) / kBlock) * 7 * sizeof(double));
     L.order = take(N * sizeof(int32_t));
+    // previous-step brackets (warm start): uint16 per (source, target)
+    L.kc_bytes = c.guess == EMPP_GUESS_PREVIOUS ? N * N * sizeof(uint16_t) : 0;
+    L.kc = L.kc_bytes ? take(L.kc_bytes) : 0;
     L.total = o;
     return L;
 }
@@ -192,8 +195,10 @@ empp_status validate(const empp_config *c)
         return fail(EMPP_EINVAL, "unknown precision %d", c->precision);
     if (c->precision == EMPP_MIXED && !kHaveMixed)
         return fail(EMPP_EUNSUPPORTED, "mixed precision is not built");
-    if (c->guess < 0 || c->guess > 3)
+    if (c->guess < 0 || c->guess > 4)
         return fail(EMPP_EINVAL, "unknown guess mode %d", c->guess);
+    if (c->guess == EMPP_GUESS_PREVIOUS && c->precision == EMPP_MIXED)
+        return fail(EMPP_EUNSUPPORTED, "warm-start brackets are implemented for the FP64 path");
     return EMPP_OK;
 }
 
@@ -220,6 +225,7 @@ struct empp_ctx {
     bool have_history = false;
     bool handed_off = false;
     bool counting = false;
+    bool kc_valid = false;  // the bracket cache holds the previous step's brackets
     int head = 0;
     int64_t step = 0;
     double t_origin = 0.0;  // T of step 0
@@ -255,6 +261,7 @@ struct empp_ctx {
     unsigned long long *counters() const { return at<unsigned long long>(L.counters); }
     double *diag() const { return at<double>(L.diag); }
     int32_t *order() const { return at<int32_t>(L.order); }
+    uint16_t *kc() const { return L.kc_bytes ? at<uint16_t>(L.kc) : nullptr; }
 };
 
 namespace {
@@ -311,6 +318,11 @@ PairParams pair_params(empp_ctx *ctx)
     p.err = ctx->err();
     p.counters = ctx->counters();
     p.guess = ctx->cfg.guess == EMPP_GUESS_MLP_PAIR ? EMPP_GUESS_MLP : ctx->cfg.guess;
+    // the bracket cache serves the step's launch only
+    if (p.guess == EMPP_GUESS_PREVIOUS)
+        p.guess = EMPP_GUESS_BISECT;
+    p.kc = nullptr;
+    p.kc_cold = 1;
     p.dt = ctx->cfg.dt;
     return p;
 }
@@ -541,6 +553,7 @@ empp_status empp_init_history_straight(empp_ctx *ctx)
     ctx->step = 0;
     ctx->t_now = ctx->t_origin;  // t0 + 0 * dt
     ctx->have_history = true;
+    ctx->kc_valid = false;
     ctx->handed_off = false;
     return EMPP_OK;
 }
@@ -599,6 +612,7 @@ empp_status empp_set_history(empp_ctx *ctx, int32_t nslots, const double *T, con
     ctx->t_now = T[D - 1];
     ctx->have_bunch = true;
     ctx->have_history = true;
+    ctx->kc_valid = false;
     ctx->handed_off = false;
     return EMPP_OK;
 }
@@ -630,7 +644,13 @@ empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
         p.order = ctx->order();
         p.m = N;
         p.kstar = nullptr;
+        if (ctx->cfg.guess == EMPP_GUESS_PREVIOUS) {
+            p.guess = EMPP_GUESS_PREVIOUS;
+            p.kc = ctx->kc();
+            p.kc_cold = ctx->kc_valid ? 0 : 1;
+        }
         HIP_TRY(launch_pair(ctx, p, false));
+        ctx->kc_valid = p.kc != nullptr;
         PushParams q{};
         q.ring_w = ctx->ring_w();
         q.ring_v = ctx->ring_v();
@@ -1271,6 +1291,8 @@ empp_status empp_set_mode(empp_ctx *ctx, int32_t precision, int32_t guess)
     empp_status st = validate(&c);
     if (st != EMPP_OK)
         return st;
+    if (guess == EMPP_GUESS_PREVIOUS && !ctx->kc())
+        return fail(EMPP_EUNSUPPORTED, "warm-start brackets need a context created with that guess mode");
     ctx->cfg.precision = precision;
     ctx->cfg.guess = guess;
     return EMPP_OK;

@@ -57,7 +57,15 @@ struct PairParams {
     double dt;
     const float *G;             // surrogate guesses: row (a >> g_shift), column source
     int32_t g_shift;            // 6: one guess per 64 consecutive targets
+    // warm start (step mode): bracket of every (source j, target slot a)
+    // from the previous step at kc[j * m + a]: back offset b* (1..D-1) or
+    // kBracketBefore.  Read by the warm-start search (kc_cold = 0) and
+    // written by it; on a cold step the bisection fills it.
+    uint16_t *kc;
+    int32_t kc_cold;
 };
+
+constexpr uint16_t kBracketBefore = 0xFFFF;
 
 struct PushParams {
     double4 *ring_w;

@@ -93,7 +93,7 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
 }  // namespace
 
 template <bool KSTAR, bool COUNT, int GUESS, int S>
-__global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
+__global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
 {
     extern __shared__ double4 lds[];
     const int D = p.D;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
     int tiles_in_acc = 0;
     int probes = 0, nbefore = 0, npairs = 0, nfall = 0;
     bool failed = false;
-    int64_t fail_j = 0;
+    int32_t fail_j = 0;  // sources number at most 2^31
     const float inv_cdt = (float)(1.0 / (kC_LIGHT * p.dt));
 
     // LDS: nbuf tile buffers of S * D records, then the light distance of
@@ -196,9 +196,25 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
         }
         __syncthreads();
     }
+    // previous-step brackets of the next tile's sources (warm start)
+    uint16_t knext[S], kcur[S];
+    auto load_brackets = [&](int64_t jt) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            knext[s] = active && jt + s < j1 ? p.kc[(jt + s) * p.m + a] : kBracketBefore;
+    };
+    if (GUESS == 4 && j0 < j1)
+        load_brackets(j0);
     int it = 0;
     for (int64_t jt = j0; jt < j1; jt += S, ++it) {
         const int ns = tile_size(jt);
+        if (GUESS == 4) {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                kcur[s] = knext[s];
+            if (jt + S < j1)
+                load_brackets(jt + S);
+        }
         double4 *cur = lds;
         if (nbuf == 2) {
             cur = lds + (it & 1) * (S * D);
@@ -222,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
             bool valid[S];
             int64_t jj[S];
             int bk[S];
-    #pragma unroll
+#pragma unroll
             for (int s = 0; s < S; ++s) {
                 jj[s] = jt + (s < ns ? s : 0);
                 valid[s] = s < ns && jj[s] != self;
@@ -232,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
                 double4 wn = cur[s * D];
                 if (valid[s] && rx == wn.x && ry == wn.y && rz == wn.z) {
                     if (!failed)
-                        fail_j = jj[s];
+                        fail_j = (int32_t)jj[s];
                     failed = true;
                     valid[s] = false;
                 }
@@ -255,12 +271,12 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
                 bool ok = lw_pair(rx, ry, rz, cur[s * D + bb], Ls[bb], v1, v2, before, p.kq, f);
                 if (valid[s]) {
                     if (ok) {
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < 6; ++k)
                             acc[k] += f[k];
                     } else {
                         if (!failed)
-                            fail_j = jj[s];
+                            fail_j = (int32_t)jj[s];
                         failed = true;
                     }
                     if (KSTAR)
@@ -272,51 +288,94 @@ __global__ __launch_bounds__(kBlock) void pair_fp64_kernel(PairParams p)
                 }
             };
 
-            if (GUESS == 0) {
-                // The paper's search: oldest sample first, then bisection of the
-                // whole history; a fixed number of halvings keeps the S searches
-                // in lockstep (extra halvings of a one-step bracket change
-                // nothing).
-                bool inside[S];
-                int xb[S];  // f(xb) <= 0; the bracket lies in (xb, xb + n]
-    #pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    inside[s] = lightcone_positive(cur[s * D + D - 1], rx, ry, rz);
-                    xb[s] = 0;
-                }
-                bool any = false;
-    #pragma unroll
-                for (int s = 0; s < S; ++s)
-                    any = any || (inside[s] && valid[s]);
-                if (__any(any)) {
-                    // halving widths depend on D only: uniform across lanes
-                    for (int n = D - 1; n > 1;) {
-                        const int half = n >> 1;
-    #pragma unroll
-                        for (int s = 0; s < S; ++s) {
-                            int m = xb[s] + half;
-                            bool f = lightcone_positive(cur[s * D + m], rx, ry, rz);
-                            xb[s] = f ? xb[s] : m;
+            if (GUESS == 0 || GUESS >= 4) {
+                if (GUESS != 4) {
+                    // The paper's search: oldest sample first, then bisection
+                    // of the whole history; a fixed number of halvings keeps
+                    // the S searches in lockstep (extra halvings of a one-step
+                    // bracket change nothing).
+                    bool inside[S];
+                    int xb[S];  // f(xb) <= 0; the bracket lies in (xb, xb + n]
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        inside[s] = lightcone_positive(cur[s * D + D - 1], rx, ry, rz);
+                        xb[s] = 0;
+                    }
+                    bool any = false;
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        any = any || (inside[s] && valid[s]);
+                    if (__any(any)) {
+                        // halving widths depend on D only: uniform across lanes
+                        for (int n = D - 1; n > 1;) {
+                            const int half = n >> 1;
+#pragma unroll
+                            for (int s = 0; s < S; ++s) {
+                                int m = xb[s] + half;
+                                bool f = lightcone_positive(cur[s * D + m], rx, ry, rz);
+                                xb[s] = f ? xb[s] : m;
+                            }
+                            n -= half;
                         }
-                        n -= half;
+                    }
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        bk[s] = inside[s] ? xb[s] + 1 : -1;
+                        if (COUNT && valid[s])
+                            probes += inside[s] ? 1 + p.nit : 1;
+                    }
+                } else {
+                    // Warm start from the previous step's bracket (back
+                    // offsets are relative to the newest slot, so a pair
+                    // whose geometry is unchanged keeps its value): confirm
+                    // it with the two samples that define it, issued
+                    // together for the S sources; a pair whose bracket moved
+                    // gallops from the old one.
+                    bool hit[S];
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        const int g = kcur[s];
+                        const bool was_before = g == kBracketBefore;
+                        const bool in_range = g >= 1 && g < D;
+                        const int ga = in_range ? g : D - 1;  // 1 <= ga <= D - 1
+                        const bool fa = lightcone_positive(cur[s * D + ga], rx, ry, rz);
+                        const bool fb = lightcone_positive(cur[s * D + ga - 1], rx, ry, rz);
+                        hit[s] = was_before ? !fa : (in_range && fa && !fb);
+                        // a bracket index leaves this block only if it is
+                        // one (the entry of an excluded pair is never
+                        // written and may hold anything)
+                        bk[s] = in_range ? g : -1;
+                        if (COUNT && valid[s])
+                            probes += was_before || g == 1 ? 1 : 2;
+                    }
+                    for (int s = 0; s < S; ++s) {
+                        if (!hit[s] && valid[s]) {
+                            const double4 *rec = cur + s * D;
+                            auto test = [&](int bb) { return lightcone_positive(rec[bb], rx, ry, rz); };
+                            const int g = kcur[s];
+                            int fb = 0;
+                            bk[s] = search_guided(test, D, g == kBracketBefore || g >= D ? (float)(D - 1) : (float)g, 6,
+                                                  probes, fb);
+                            nfall += fb;
+                        }
                     }
                 }
-    #pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    bk[s] = inside[s] ? xb[s] + 1 : -1;
-                    if (COUNT && valid[s])
-                        probes += inside[s] ? 1 + p.nit : 1;
+                if (GUESS >= 4) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        if (valid[s])
+                            p.kc[jj[s] * p.m + a] = bk[s] < 0 ? kBracketBefore : (uint16_t)bk[s];
                 }
                 double4 v1[S], v2[S];
-    #pragma unroll
+#pragma unroll
                 for (int s = 0; s < S; ++s)
                     load_v(s, bk[s], v1[s], v2[s]);
-    #pragma unroll
+#pragma unroll
                 for (int s = 0; s < S; ++s)
                     finish(s, bk[s], v1[s], v2[s]);
             } else {
                 // guided searches, one source at a time
-    #pragma unroll
+#pragma unroll
                 for (int s = 0; s < S; ++s) {
                     int b = -1;
                     if (valid[s]) {
@@ -422,7 +481,17 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
         else if (p.guess == 1) EMPP_BY_TILE(K, C, 1);                                                        \
         else EMPP_BY_TILE(K, C, 0);                                                                          \
     } while (0)
-    if (kstar) {
+    if (p.guess == 4) {
+        // warm start: step mode only (no per-pair k* output); the first
+        // step of a run bisects and fills the cache (search mode 5)
+        if (kstar || !p.kc || p.x)
+            return hipErrorInvalidValue;
+        if (p.kc_cold) {
+            if (count) EMPP_BY_TILE(false, true, 5); else EMPP_BY_TILE(false, false, 5);
+        } else {
+            if (count) EMPP_BY_TILE(false, true, 4); else EMPP_BY_TILE(false, false, 4);
+        }
+    } else if (kstar) {
         if (count) EMPP_BY_GUESS(true, true); else EMPP_BY_GUESS(true, false);
     } else {
         if (count) EMPP_BY_GUESS(false, true); else EMPP_BY_GUESS(false, false);
