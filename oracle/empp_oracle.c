@@ -89,19 +89,25 @@ static void neumaier_add(double *sum, double *comp, double x)
 /* ---- Sec. 2.2: light-cone sign of a stored sample --------------------------
  * f_k = c (t - T_k) - |r - w_k|.  The bracket needs only its sign; it is
  * evaluated on squares so no square root enters the decision:
- *   f_k > 0  <=>  L*L > (dx*dx + dy*dy) + dz*dz,   L = c*(t - T_k).
- * The association order is fixed (and the build forbids contraction) so
- * that the GPU path can reproduce the decision bit for bit.                */
+ *   f_k > 0  <=>  L*L - dx*dx - dy*dy - dz*dz > 0,   L = c*(t - T_k),
+ * with L*L rounded once and the three squares taken off by fused
+ * multiply-adds (C99 fma: one rounding each), in the order x, y, z.  The
+ * expression is fixed (and the build forbids other contraction) so that
+ * the GPU path can reproduce the decision bit for bit.                      */
 static int lightcone_positive(const double r[3], const double wk[3], double t, double Tk)
 {
     double L = C_LIGHT * (t - Tk);
     double dx = r[0] - wk[0];
     double dy = r[1] - wk[1];
     double dz = r[2] - wk[2];
+    double q = L * L;
+    q = fma(-dx, dx, q);
+    q = fma(-dy, dy, q);
+    q = fma(-dz, dz, q);
 #ifdef MUT_TIE_NEWER
-    return L * L >= (dx * dx + dy * dy) + dz * dz;
+    return q >= 0.0;
 #else
-    return L * L > (dx * dx + dy * dy) + dz * dz;
+    return q > 0.0;
 #endif
 }
 

@@ -88,6 +88,25 @@ struct PushParams {
     int32_t self_field; // 0: stage-II transport (E = 0, B = B_geo only)
 };
 
+// Block of a pair-kernel launch -> (target block bx, source chunk split).
+// The grid is one-dimensional, nbx * nsplit blocks.  Workgroups go to the 8
+// XCDs round-robin by linear index; when the chunk count is a multiple of 8
+// every chunk is given to one XCD, so the target blocks that stage its
+// histories run there together and share that XCD's L2.
+__device__ inline void pair_block_coords(int nbx, int nsplit, int &bx, int &split)
+{
+    const int L = blockIdx.x;
+    if ((nsplit & 7) == 0) {
+        const int xcd = L & 7, k = L >> 3;
+        const int round = k / nbx;
+        split = xcd + 8 * round;
+        bx = k - round * nbx;
+    } else {
+        split = L / nbx;
+        bx = L - split * nbx;
+    }
+}
+
 // Error word: err[0] = (target << 32 | source) of the lowest failing pair
 // (atomicMin), err[1] = OR of status bits.
 constexpr unsigned long long kErrCoincident = 1ull;

@@ -7,17 +7,20 @@
 namespace empp {
 
 // Staged history record of one source at one logical slot:
-// {x, y, z, L2} with L2 = L*L, L = c (t - T_k) the light distance back to the
-// slot.  The sign test f_k > 0 <=> L*L > (dx*dx + dy*dy) + dz*dz is evaluated
-// without fused multiply-adds and in this association, so it rounds
-// exactly like a plain IEEE evaluation of the same expression.
+// {x, y, z, L2} with L2 = L*L (rounded once), L = c (t - T_k) the light
+// distance back to the slot.  The sign test f_k > 0 is
+// L2 - dx*dx - dy*dy - dz*dz > 0 with the three squares taken off by fused
+// multiply-adds in the order x, y, z: one rounding per step, the same
+// decision as any IEEE evaluation of that expression.
 __device__ inline bool lightcone_positive(double4 rec, double rx, double ry, double rz)
 {
-#pragma clang fp contract(off)
     double dx = rx - rec.x;
     double dy = ry - rec.y;
     double dz = rz - rec.z;
-    return rec.w > (dx * dx + dy * dy) + dz * dz;
+    double q = __builtin_fma(-dx, dx, rec.w);
+    q = __builtin_fma(-dy, dy, q);
+    q = __builtin_fma(-dz, dz, q);
+    return q > 0.0;
 }
 
 // Bisection of the paper: test the oldest sample first (if it is not

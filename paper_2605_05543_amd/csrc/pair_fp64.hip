@@ -96,11 +96,15 @@ template <bool KSTAR, bool COUNT, int GUESS, int S>
 __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
 {
     extern __shared__ double4 lds[];
+    // LDS address of the dynamic buffer (32-bit, for offset arithmetic)
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)lds;
     const int D = p.D;
     const int tid = threadIdx.x;
-    const int64_t a = (int64_t)blockIdx.x * kBlock + tid;
+    const int nbx = (int)((p.m + kBlock - 1) / kBlock);
+    int bxi, split;
+    pair_block_coords(nbx, p.nsplit, bxi, split);
+    const int64_t a = (int64_t)bxi * kBlock + tid;
     const bool active = a < p.m;
-    const int split = blockIdx.y;
     const int64_t j0 = (int64_t)split * p.src_per_split;
     int64_t j1 = j0 + p.src_per_split;
     if (j1 > p.n_src)
@@ -295,11 +299,14 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                     // the S searches in lockstep (extra halvings of a one-step
                     // bracket change nothing).
                     bool inside[S];
-                    int xb[S];  // f(xb) <= 0; the bracket lies in (xb, xb + n]
+                    // LDS byte address of the record of xb: f(xb) <= 0, the
+                    // bracket lies in (xb, xb + n]
+                    uint32_t xo[S];
+                    const uint32_t cur0 = (uint32_t)(cur - lds);
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
                         inside[s] = lightcone_positive(cur[s * D + D - 1], rx, ry, rz);
-                        xb[s] = 0;
+                        xo[s] = lds_base + (cur0 + (uint32_t)(s * D)) * (uint32_t)sizeof(double4);
                     }
                     bool any = false;
 #pragma unroll
@@ -309,18 +316,22 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                         // halving widths depend on D only: uniform across lanes
                         for (int n = D - 1; n > 1;) {
                             const int half = n >> 1;
+                            const uint32_t hb = (uint32_t)half * (uint32_t)sizeof(double4);
 #pragma unroll
                             for (int s = 0; s < S; ++s) {
-                                int m = xb[s] + half;
-                                bool f = lightcone_positive(cur[s * D + m], rx, ry, rz);
-                                xb[s] = f ? xb[s] : m;
+                                const uint32_t mo = xo[s] + hb;
+                                typedef double dv4 __attribute__((ext_vector_type(4)));
+                                const dv4 v = *(const __attribute__((address_space(3))) dv4 *)(uintptr_t)mo;
+                                const double4 rec = make_double4(v.x, v.y, v.z, v.w);
+                                xo[s] = lightcone_positive(rec, rx, ry, rz) ? xo[s] : mo;
                             }
                             n -= half;
                         }
                     }
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        bk[s] = inside[s] ? xb[s] + 1 : -1;
+                        bk[s] = inside[s] ? (int)((xo[s] - lds_base) / (uint32_t)sizeof(double4) - cur0) - s * D + 1
+                                          : -1;
                         if (COUNT && valid[s])
                             probes += inside[s] ? 1 + p.nit : 1;
                     }
@@ -464,7 +475,10 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
 {
     PairParams p = p0;
     p.nbuf = pair_fp64_nbuf(p.D, p.tile);
-    dim3 grid((unsigned)((p.m + kBlock - 1) / kBlock), (unsigned)p.nsplit);
+    const int64_t nblocks = (p.m + kBlock - 1) / kBlock * p.nsplit;
+    if (nblocks < 1 || nblocks > INT32_MAX)
+        return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)nblocks);
     size_t lds = (size_t)p.nbuf * p.tile * p.D * sizeof(double4) + (size_t)p.D * sizeof(double);
 #define EMPP_LAUNCH(K, C, G, S)                                                                              \
     do {                                                                                                    \

@@ -129,9 +129,11 @@ __global__ __launch_bounds__(kBlock) void pair_mixed_kernel(PairParams p)
     double *Ls = reinterpret_cast<double *>(ldsf + S * D);
     double4 *anchor = reinterpret_cast<double4 *>(Ls + D);
     const int tid = threadIdx.x;
-    const int64_t a = (int64_t)blockIdx.x * kBlock + tid;
+    const int nbx = (int)((p.m + kBlock - 1) / kBlock);
+    int bxi, split;
+    pair_block_coords(nbx, p.nsplit, bxi, split);
+    const int64_t a = (int64_t)bxi * kBlock + tid;
     const bool active = a < p.m;
-    const int split = blockIdx.y;
     const int64_t j0 = (int64_t)split * p.src_per_split;
     int64_t j1 = j0 + p.src_per_split;
     if (j1 > p.n_src)
@@ -364,7 +366,10 @@ hipError_t launch_pair_mixed(const PairParams &p0, hipStream_t stream, bool ksta
 {
     PairParams p = p0;
     p.tile = pair_mixed_tile(p.D);
-    dim3 grid((unsigned)((p.m + kBlock - 1) / kBlock), (unsigned)p.nsplit);
+    const int64_t nblocks = (p.m + kBlock - 1) / kBlock * p.nsplit;
+    if (nblocks < 1 || nblocks > INT32_MAX)
+        return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)nblocks);
     size_t lds = (size_t)p.tile * p.D * sizeof(float4) + (size_t)p.D * sizeof(double) + 4 * sizeof(double4);
 #define EMPP_LAUNCH(K, C, G, S)                                                                              \
     do {                                                                                                    \

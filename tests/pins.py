@@ -288,17 +288,33 @@ def pin_bracket_bruteforce(orc):
     return ok, f"{n_in} in-history, {n_before} before; mismatches {bad[:4]}; root err/dt {worst_root:.2e}"
 
 
+def _exact_light_delay(L0):
+    """A delay d with c*d == L0 exactly in double precision."""
+    d = L0 / C
+    for _ in range(64):
+        p = C * d
+        if p == L0:
+            return d
+        d = np.nextafter(d, np.inf if p < L0 else -np.inf)
+    raise AssertionError("no exact delay found")
+
+
 def pin_tie_goes_older(orc):
     """An exact tie |r - w_k| == c (t - T_k) sends the bracket to the older
-    side: the retarded time lies in [t_0, t_m] when c dt <= |r - w(t_m)|."""
+    side: the retarded time lies in [t_0, t_m] when c dt <= |r - w(t_m)|.
+    The tie is exact in floating point too: the light distance is 2^-12 m,
+    whose square is a double, and the target sits that far from the
+    sample."""
     ns = 16
     T, w, v = bunch.uniform_history(ns, 1e-13, np.zeros((3, 1)), np.zeros((3, 1)))
     t = T[-1]
-    s = ns - 1 - 5  # tie at 5 slots back
-    L = C * (t - T[s])
-    x = np.array([[L], [0.0], [0.0]])
+    L0 = 2.0**-12  # 0.244 mm: 8.14 steps of 1e-13 s
+    s = ns - 1 - 8  # tie at 8 slots back
+    T[s] = t - _exact_light_delay(L0)
+    assert T[s - 1] < T[s] < T[s + 1] and C * (t - T[s]) == L0
+    x = np.array([[L0], [0.0], [0.0]])
     ks = orc.retarded(T, w, v, t, x)["kstar"]
-    return int(ks[0, 0]) == 6, f"kstar at an exact tie {int(ks[0, 0])} (expected 6)"
+    return int(ks[0, 0]) == 9, f"kstar at an exact tie {int(ks[0, 0])} (expected 9)"
 
 
 def _circle_case(steps_per_period, ns, rho=1e-3, beta=0.6, ntarget=240, seed=41):
