@@ -212,9 +212,11 @@ empp_status empp_get_timing(empp_ctx *ctx, empp_timing *out);
  * source's newest velocity / c (3), its displacement over the last 4 steps
  * / (c (T_n - T_{n-4})) (3) and log1p((t - T_n)/dt) (1).  With guess mode
  * EMPP_GUESS_MLP it is evaluated once per (group of 64 consecutive targets
- * in the spatial order, source) at the group centroid and scaled by each
- * target's own distance; the exact search then finishes every bracket, so
- * the network changes cost, never results.  Not part of the paper's
+ * -- in the spatial order when stepping --, source) at the group centroid;
+ * its ratio to the straight-line value there (a source coasting with its
+ * newest velocity) scales each target's own straight-line look-back.  The
+ * exact search then finishes every bracket, so the network changes cost,
+ * never results.  Not part of the paper's
  * method.  Parameters: the flat vector W1[128][10], b1[128], W2[128][128],
  * b2[128], W3[128], b3 (18049 floats, FP32 masters).                     */
 typedef struct {

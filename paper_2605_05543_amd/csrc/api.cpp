@@ -380,8 +380,11 @@ hipError_t launch_guesses(empp_ctx *ctx, PairParams &p, float *G_pair = nullptr,
             gp.D = ctx->cfg.depth;
             gp.head = ctx->head;
             gp.inv_sigma = 1.0 / ctx->sg.sigma_ref;
+            gp.ratio = 0;
             p.G = G_pair;
+            p.g_groups = p.m;
             p.g_shift = 0;
+            p.g_ratio = 0;
             return launch_mlp_group_guess(ctx->sg.net, gp, G_pair, ctx->stream);
         });
     }
@@ -403,8 +406,11 @@ hipError_t launch_guesses(empp_ctx *ctx, PairParams &p, float *G_pair = nullptr,
         gp.D = ctx->cfg.depth;
         gp.head = ctx->head;
         gp.inv_sigma = 1.0 / ctx->sg.sigma_ref;
+        gp.ratio = 1;
         p.G = ctx->sg.G;
+        p.g_groups = gp.ngroups;
         p.g_shift = 6;
+        p.g_ratio = 1;
         return launch_mlp_group_guess(ctx->sg.net, gp, ctx->sg.G, ctx->stream);
     });
 }

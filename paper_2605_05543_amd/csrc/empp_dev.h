@@ -55,8 +55,10 @@ struct PairParams {
     int32_t guess;
     float dt_inv_f;
     double dt;
-    const float *G;             // surrogate guesses: row (a >> g_shift), column source
+    const float *G;             // surrogate guesses G[source * g_groups + (a >> g_shift)]
+    int64_t g_groups;           // target groups of the launch
     int32_t g_shift;            // 6: one guess per 64 consecutive targets
+    int32_t g_ratio;            // G is a factor on the straight-line look-back
     // warm start (step mode): bracket of every (source j, target slot a)
     // from the previous step at kc[j * m + a]: back offset b* (1..D-1) or
     // kBracketBefore.  Read by the warm-start search (kc_cold = 0) and

@@ -41,6 +41,12 @@ __device__ __forceinline__ unsigned short bf16_bits(float f)
 __device__ __forceinline__ float bf16_value(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ __forceinline__ float silu(float x) { return x / (1.0f + __expf(-x)); }
+// Inference form: hardware exp2 and reciprocal (a few ulp of float, far
+// below the bf16 rounding the activations then take).
+__device__ __forceinline__ float silu_fast(float x)
+{
+    return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * x));
+}
 __device__ __forceinline__ float silu_grad(float x)
 {
     float s = 1.0f / (1.0f + __expf(-x));
@@ -48,23 +54,27 @@ __device__ __forceinline__ float silu_grad(float x)
 }
 
 // Network weights staged in LDS: W1 [128][16] (K padded, column 10 is 0),
-// W2 [128][128], the bf16-rounded biases and W3 as floats.
+// W2 [128][128], the bf16-rounded biases and W3 as floats.  Rows are padded
+// (to 20 and 132 halfwords) so that the 16 rows one A-fragment read touches
+// start on distinct banks.
+constexpr int kW1S = 20, kW2S = 132;
 struct NetLds {
-    unsigned short W1[kHid * 16];
-    unsigned short W2[kHid * kHid];
+    unsigned short W1[kHid * kW1S];
+    unsigned short W2[kHid * kW2S];
     float b1[kHid], b2[kHid], W3[kHid], b3;
 };
 
 __device__ void load_net(NetLds &s, const MlpPacked *net)
 {
+    // two halfwords per copy; rows keep their padded stride
     const uint32_t *src1 = reinterpret_cast<const uint32_t *>(net->W1);
     uint32_t *dst1 = reinterpret_cast<uint32_t *>(s.W1);
     for (int i = threadIdx.x; i < kHid * 16 / 2; i += blockDim.x)
-        dst1[i] = src1[i];
+        dst1[(i / 8) * (kW1S / 2) + i % 8] = src1[i];
     const uint32_t *src2 = reinterpret_cast<const uint32_t *>(net->W2);
     uint32_t *dst2 = reinterpret_cast<uint32_t *>(s.W2);
     for (int i = threadIdx.x; i < kHid * kHid / 2; i += blockDim.x)
-        dst2[i] = src2[i];
+        dst2[(i / (kHid / 2)) * (kW2S / 2) + i % (kHid / 2)] = src2[i];
     for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
         s.b1[i] = net->b1[i];
         s.b2[i] = net->b2[i];
@@ -114,7 +124,7 @@ __device__ __forceinline__ float net_forward(const NetLds &s, s4 xb, FwdState &s
     s4 h1[8];
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
-        s4 a = lds_s4(&s.W1[(mt * 16 + col) * 16 + 4 * g]);
+        s4 a = lds_s4(&s.W1[(mt * 16 + col) * kW1S + 4 * g]);
         f4 d = mfma16(a, xb, f4{0, 0, 0, 0});
         float v[4];
 #pragma unroll
@@ -122,7 +132,7 @@ __device__ __forceinline__ float net_forward(const NetLds &s, s4 xb, FwdState &s
             float pre = d[r] + s.b1[mt * 16 + 4 * g + r];
             if (KEEP)
                 st.a1[mt][r] = pre;
-            v[r] = silu(pre);
+            v[r] = KEEP ? silu(pre) : silu_fast(pre);
         }
         h1[mt] = pack4(v[0], v[1], v[2], v[3]);
         if (KEEP)
@@ -130,25 +140,36 @@ __device__ __forceinline__ float net_forward(const NetLds &s, s4 xb, FwdState &s
     }
     // layer 2: H2^T = W2 H1^T
     float z = 0.0f;
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt) {
+    auto tile2 = [&](int mt) {
         f4 acc = {0, 0, 0, 0};
 #pragma unroll
         for (int kt = 0; kt < 8; ++kt) {
-            s4 a = lds_s4(&s.W2[(mt * 16 + col) * kHid + kt * 16 + 4 * g]);
+            s4 a = lds_s4(&s.W2[(mt * 16 + col) * kW2S + kt * 16 + 4 * g]);
             acc = mfma16(a, h1[kt], acc);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             int j = mt * 16 + 4 * g + r;
             float pre = acc[r] + s.b2[j];
-            float h = silu(pre);
+            float h = KEEP ? silu(pre) : silu_fast(pre);
             if (KEEP) {
                 st.a2[mt][r] = pre;
                 st.h2[mt][r] = h;
             }
             z += s.W3[j] * h;
         }
+    };
+    if (KEEP) {
+        // training keeps every tile's values: static register indices
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+            tile2(mt);
+    } else {
+        // inference: four output tiles at a time bounds the A fragments of
+        // W2 held in registers
+#pragma unroll 4
+        for (int mt = 0; mt < 8; ++mt)
+            tile2(mt);
     }
     // layer 3: sum the four lane groups that share a row
     z += __shfl_xor(z, 16);
@@ -207,6 +228,7 @@ struct TrainLds {
     unsigned short XeT[4][16 * 16];        // [X | 1]^T [k][i] (column 10 of X is 1)
     unsigned short dzT[4][16 * 16];        // [dz | 0]^T [k][i] (k = 0: dz_i)
 };
+static_assert(sizeof(TrainLds) <= 160 * 1024, "training tile exceeds the 160 KiB of LDS");
 
 __global__ __launch_bounds__(256) void mlp_train_kernel(const MlpPacked *net, const float *X, const float *y,
                                                         int64_t n, float scale, float *part)
@@ -217,7 +239,7 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(const MlpPacked *net, co
     __syncthreads();
     for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x) {
         int m = i / kHid, k = i % kHid;
-        s.W2T[m * kHid + k] = s.net.W2[k * kHid + m];
+        s.W2T[m * kHid + k] = s.net.W2[k * kW2S + m];
     }
     __syncthreads();
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -495,28 +517,29 @@ __global__ __launch_bounds__(256) void mlp_group_guess_kernel(const MlpPacked *n
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t rows = p.ngroups * p.N;
     const int D = p.D, h = p.head;
-    const double c = kC_LIGHT;
+    int h4 = h - 4;
+    h4 += h4 < 0 ? D : 0;
+    const double inv_c = 1.0 / kC_LIGHT;
+    const double inv_span = 1.0 / (kC_LIGHT * (p.T[h] - p.T[h4]));
     for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * 16; base < rows; base += (int64_t)gridDim.x * 64) {
         int64_t row = base + (l & 15);
         float f[kIn];
         if (row < rows) {
-            int64_t grp = row / p.N, j = row % p.N;
+            // source-major rows: a tile of 16 rows shares one source
+            int64_t j = row / p.ngroups, grp = row - j * p.ngroups;
             double3 cen = p.centroid[grp];
             double4 wn = p.ring_w[j * D + h];
             double4 vn = p.ring_v[j * D + h];
-            int h4 = h - 4;
-            h4 += h4 < 0 ? D : 0;
             double4 w4 = p.ring_w[j * D + h4];
-            double span = c * (p.T[h] - p.T[h4]);
             f[0] = (float)((cen.x - wn.x) * p.inv_sigma);
             f[1] = (float)((cen.y - wn.y) * p.inv_sigma);
             f[2] = (float)((cen.z - wn.z) * p.inv_sigma);
-            f[3] = (float)(vn.x / c);
-            f[4] = (float)(vn.y / c);
-            f[5] = (float)(vn.z / c);
-            f[6] = (float)((wn.x - w4.x) / span);
-            f[7] = (float)((wn.y - w4.y) / span);
-            f[8] = (float)((wn.z - w4.z) / span);
+            f[3] = (float)(vn.x * inv_c);
+            f[4] = (float)(vn.y * inv_c);
+            f[5] = (float)(vn.z * inv_c);
+            f[6] = (float)((wn.x - w4.x) * inv_span);
+            f[7] = (float)((wn.y - w4.y) * inv_span);
+            f[8] = (float)((wn.z - w4.z) * inv_span);
             f[9] = 0.0f;
         } else {
 #pragma unroll
@@ -525,8 +548,22 @@ __global__ __launch_bounds__(256) void mlp_group_guess_kernel(const MlpPacked *n
         }
         FwdState st;
         float zz = net_forward<false>(s, feature_operand(f), st);
-        if (l < 16 && row < rows)
-            G[row] = __expf(zz);
+        if (l < 16 && row < rows) {
+            float g = __expf(zz);
+            if (p.ratio) {
+                // straight-line look-back from the centroid, in units of
+                // |centroid - w_n| (f[0..2] are that offset over sigma)
+                const float sig = (float)(1.0 / p.inv_sigma);
+                const float Rx = f[0] * sig, Ry = f[1] * sig, Rz = f[2] * sig;
+                const float R2 = Rx * Rx + Ry * Ry + Rz * Rz;
+                const float rb = Rx * f[3] + Ry * f[4] + Rz * f[5];
+                const float g2 = 1.0f - (f[3] * f[3] + f[4] * f[4] + f[5] * f[5]);
+                const float sb = (rb + sqrtf(rb * rb + g2 * R2)) / g2;
+                const float gb = sb * __builtin_amdgcn_rsqf(R2);
+                g = R2 > 0.0f && gb > 0.0f ? g / gb : 1.0f;
+            }
+            G[row] = g;
+        }
     }
 }
 

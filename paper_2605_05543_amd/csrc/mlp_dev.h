@@ -48,6 +48,10 @@ struct GuessParams {
     int32_t D;
     int32_t head;
     double inv_sigma;
+    // 0: G = the network's c (t - t_r) / |r - w_n|; 1: G = that prediction
+    // divided by the straight-line value at the same point (the group's
+    // correction factor, applied per target to its own straight-line delay)
+    int32_t ratio;
 };
 
 }  // namespace empp

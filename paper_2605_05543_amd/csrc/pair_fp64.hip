@@ -397,10 +397,17 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                         if (GUESS == 2) {
                             double4 vn = p.ring_v[jj[s] * D + p.head];
                             g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
+                        } else if (p.g_ratio) {
+                            // surrogate, one evaluation per group: the group's
+                            // correction factor to straight-line motion times
+                            // this target's straight-line look-back
+                            double4 vn = p.ring_v[jj[s] * D + p.head];
+                            float gh = p.G[jj[s] * p.g_groups + (a >> p.g_shift)];
+                            g = gh * ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
                         } else {
-                            // surrogate: predicted c (t - t_r) / |r - w_n| times this target's distance
+                            // surrogate per pair: predicted c (t - t_r) / |r - w_n| times the distance
                             float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
-                            float gh = p.G[(a >> p.g_shift) * p.n_src + jj[s]];
+                            float gh = p.G[jj[s] * p.g_groups + (a >> p.g_shift)];
                             g = gh * __builtin_amdgcn_sqrtf(Rx * Rx + Ry * Ry + Rz * Rz) * inv_cdt;
                         }
                         int fb = 0;

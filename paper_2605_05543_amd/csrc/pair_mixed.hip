@@ -277,9 +277,16 @@ __global__ __launch_bounds__(kBlock) void pair_mixed_kernel(PairParams p)
                 if (GUESS == 2) {
                     double4 vn = p.ring_v[jj[s] * D + p.head];
                     g = ballistic_steps((double)Rx[s], (double)Ry[s], (double)Rz[s], vn, inv_cdt);
+                } else if (p.g_ratio) {
+                    // surrogate, one evaluation per group: the group's
+                    // correction factor to straight-line motion times this
+                    // target's straight-line look-back
+                    double4 vn = p.ring_v[jj[s] * D + p.head];
+                    float gh = p.G[jj[s] * p.g_groups + (a >> p.g_shift)];
+                    g = gh * ballistic_steps((double)Rx[s], (double)Ry[s], (double)Rz[s], vn, inv_cdt);
                 } else {
-                    // surrogate: predicted c (t - t_r) / |r - w_n| times this target's distance
-                    float gh = p.G[(a >> p.g_shift) * p.n_src + jj[s]];
+                    // surrogate per pair: predicted c (t - t_r) / |r - w_n| times the distance
+                    float gh = p.G[jj[s] * p.g_groups + (a >> p.g_shift)];
                     g = gh * __builtin_amdgcn_sqrtf(Rx[s] * Rx[s] + Ry[s] * Ry[s] + Rz[s] * Rz[s]) * inv_cdt;
                 }
                 int fb = 0;

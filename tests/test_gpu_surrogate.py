@@ -153,8 +153,10 @@ def test_what_the_network_gains():
     C2 and C3 bunches against the method without it.  Iterations (sign
     tests per pair) over 1024 seeded targets x all sources for the paper's
     bisection, the network evaluated per pair, the network amortised over
-    groups of 64 targets, and the closed-form ballistic guess; k* and fields
-    are identical in all four."""
+    groups of 64 targets (its correction to the straight-line delay at the
+    group centroid applied to each target's straight-line delay), and the
+    straight-line (ballistic) guess alone; k* and fields are identical in
+    all four."""
     from paper_2605_05543_amd import surrogate
     from paper_2605_05543_amd._lib import EMPP_GUESS_BALLISTIC, EMPP_GUESS_BISECT, EMPP_GUESS_MLP, EMPP_GUESS_MLP_PAIR
 
@@ -190,3 +192,4 @@ def test_what_the_network_gains():
         assert np.array_equal(out[name][0], out["bisect"][0]) and np.array_equal(out[name][1], out["bisect"][1])
     assert rep["loss_last"] < 0.05 * rep["loss_first"]
     assert out["mlp-pair"][3] < out["bisect"][3]
+    assert out["mlp-group"][3] < out["bisect"][3]
