@@ -83,6 +83,8 @@ class Oracle:
                                   ctypes.c_int, _P]
         L.oracle_diag.argtypes = [_I64, _P, _P, _D, _P]
         L.oracle_diag.restype = None
+        L.oracle_transport.argtypes = [_I64, _D, _D, _I32, _D, _D, _D, _D, _P, _P, _P, _I64, _P]
+        L.oracle_transport.restype = ctypes.c_int
         L.oracle_max_threads.argtypes = []
         self.L = L
         c = np.zeros(6)
@@ -155,6 +157,17 @@ class Oracle:
         if st != OR_OK:
             raise OracleError(st)
         return T, w, v
+
+    def transport(self, y, u, t, *, q, mass, dt_max, frac, nsteps, ext_field=0, b0=0.0, re=0.0):
+        """Stage II (E = 0, B = B_geo): returns (y, u, t, last dt)."""
+        y, u = _f64(y).copy(), _f64(u).copy()
+        tt = np.array([float(t)])
+        dl = np.zeros(1)
+        st = self.L.oracle_transport(y.shape[1], float(q), float(mass), int(ext_field), float(b0), float(re),
+                                     float(dt_max), float(frac), _ptr(y), _ptr(u), _ptr(tt), int(nsteps), _ptr(dl))
+        if st != OR_OK:
+            raise OracleError(st)
+        return y, u, float(tt[0]), float(dl[0])
 
     def diag(self, y, u, mass):
         out = np.zeros(8)

@@ -617,6 +617,71 @@ int oracle_step(int64_t N, int32_t D, double q, double mass, double dt, double t
     return st;
 }
 
+/* Stage II of Sec. 2.7: after the switch the self-field is dropped and the
+ * particles move in the prescribed field alone, E = 0 and B = B_geo(y)
+ * (Sec. 2.6; B = 0 without an external field), advanced by the same
+ * Higuera-Cary update and drift y += v dt as in Stage I.  The paper lets the
+ * step grow but gives no rule; the reading taken here is a fixed fraction
+ * of the shortest gyro-period in the bunch, evaluated before every step,
+ *   dt = min(dt_max, gyro_k * min_i gamma_i / |B(y_i)|),
+ *   gyro_k = frac * 2 pi m / |q|   (the period is 2 pi gamma m / (|q| B)),
+ * and dt = dt_max when no particle sees a field.  *t advances by each dt;
+ * dt_last returns the last step's dt.                                      */
+int oracle_transport(int64_t N, double q, double mass, int32_t ext_field, double b0, double re,
+                     double dt_max, double frac, double *y, double *u, double *t, int64_t nsteps,
+                     double *dt_last)
+{
+    if (N < 1 || !(dt_max > 0.0) || !(frac > 0.0) || nsteps < 0 || q == 0.0)
+        return OR_EINVAL;
+    double *Bg = (double *)calloc((size_t)(3 * N), sizeof(double));
+    if (!Bg)
+        return OR_EINVAL;
+    const double gyro_k = frac * 2.0 * M_PI * mass / fabs(q);
+    const double zero[3] = {0.0, 0.0, 0.0};
+    for (int64_t step = 0; step < nsteps; ++step) {
+        if (ext_field == 1)
+            oracle_dipole(b0, re, N, y, Bg);
+        double key_min = INFINITY;
+        for (int64_t i = 0; i < N; ++i) {
+            double ui[3] = {u[i], u[N + i], u[2 * N + i]};
+            double Bi[3] = {Bg[i], Bg[N + i], Bg[2 * N + i]};
+            double g = sqrt(1.0 + dot3(ui, ui) / (C_LIGHT * C_LIGHT));
+            double bm = sqrt(dot3(Bi, Bi));
+#ifdef MUT_TRANSPORT_DT_NO_GAMMA
+            g = 1.0;
+#endif
+            double key = bm > 0.0 ? g / bm : INFINITY;
+            if (key < key_min)
+                key_min = key;
+        }
+        double dt = dt_max;
+        double d = gyro_k * key_min;
+        if (d < dt)
+            dt = d;
+        for (int64_t i = 0; i < N; ++i) {
+            double ui[3] = {u[i], u[N + i], u[2 * N + i]};
+            double Bi[3] = {Bg[i], Bg[N + i], Bg[2 * N + i]};
+            double vi[3];
+#ifdef MUT_TRANSPORT_OLD_V
+            velocity_of(ui, vi);
+            hc_one(q, mass, dt, ui, zero, Bi);
+#else
+            hc_one(q, mass, dt, ui, zero, Bi);
+            velocity_of(ui, vi);
+#endif
+            for (int c = 0; c < 3; ++c) {
+                u[c * N + i] = ui[c];
+                y[c * N + i] += vi[c] * dt;
+            }
+        }
+        *t += dt;
+        if (dt_last)
+            *dt_last = dt;
+    }
+    free(Bg);
+    return OR_OK;
+}
+
 /* Diagnostics (Sec. 2.5 RMS sizes, Sec. 2.7 mean kinetic energy, and the
  * weighted centroid), all weights 1:
  *   out = { sigma_x, sigma_y, sigma_z, sigma_xy, xbar, ybar, zbar, Ebar }

@@ -510,8 +510,76 @@ def pin_diag(orc):
     return err < 1e-10, f"diag rel err {err:.2e}"
 
 
+def pin_transport_free_and_dt_rule(orc):
+    """Stage II without a field is free streaming (u unchanged, y = y0 + v t,
+    dt = dt_max).  In the dipole the first step is the stated fraction of
+    the gyro-period 2 pi gamma m / (|q| B) at the equator, where
+    B = b0 (re / r)^3; a large fraction is capped at dt_max."""
+    rng = np.random.default_rng(61)
+    y0 = rng.standard_normal((3, 4)) * 1e-3
+    u0 = rng.standard_normal((3, 4)) * C
+    y, u, t, dl = orc.transport(y0, u0, 0.0, q=-QE, mass=ME, dt_max=1e-9, frac=0.05, nsteps=100)
+    g = np.sqrt(1 + (u0**2).sum(0) / C**2)
+    free = float(np.max(np.abs(y - (y0 + u0 / g * 1e-7))) / 1e-7 / C)
+    same_u = bool(np.array_equal(u, u0))
+    r = 3 * bunch.R_EARTH
+    ye = np.array([[r], [0.0], [0.0]])
+    ue = np.array([[0.0], [2.0 * C], [0.0]])
+    ge = math.sqrt(1 + 4.0)
+    Be = 3.12e-5 * (bunch.R_EARTH / r) ** 3
+    _, _, _, d1 = orc.transport(ye, ue, 0.0, q=-QE, mass=ME, dt_max=1.0, frac=1 / 32, nsteps=1, ext_field=1,
+                                b0=3.12e-5, re=bunch.R_EARTH)
+    want = 2 * math.pi * ge * ME / (QE * Be) / 32
+    # the drift takes the velocity after the kick
+    y1, u1, _, _ = orc.transport(ye, ue, 0.0, q=-QE, mass=ME, dt_max=1.0, frac=1 / 32, nsteps=1, ext_field=1,
+                                 b0=3.12e-5, re=bunch.R_EARTH)
+    uk = orc.hc(-QE, ME, d1, ue, np.zeros((3, 1)), orc.dipole(3.12e-5, bunch.R_EARTH, ye))
+    gk = math.sqrt(1 + float((uk**2).sum()) / C**2)
+    drift = float(np.max(np.abs(y1 - (ye + uk / gk * d1))))
+    _, _, _, d2 = orc.transport(ye, ue, 0.0, q=-QE, mass=ME, dt_max=1e-7, frac=1 / 32, nsteps=1, ext_field=1,
+                                b0=3.12e-5, re=bunch.R_EARTH)
+    e1 = abs(d1 / want - 1)
+    ok = (free < 1e-13 and same_u and dl == 1e-9 and abs(t - 1e-7) < 1e-21 and e1 < 1e-13 and d2 == 1e-7
+          and drift == 0.0 and np.array_equal(u1, uk))
+    return ok, (f"free streaming err {free:.1e}, u unchanged {same_u}; gyro dt rel err {e1:.1e}, capped {d2}; "
+                f"kick-then-drift err {drift:.1e} m")
+
+
+def pin_transport_mirror(orc):
+    """Stage II in the dipole: a 1 MeV electron leaving the equator at
+    3 R_E with pitch angle 30 degrees keeps |u| (a pure magnetic push) and
+    mirrors where B = B_eq / sin^2(30 deg) = 4 B_eq (conservation of the
+    magnetic moment p_perp^2 / B, the gyroradius being 1e-4 of the field
+    scale)."""
+    r = 3 * bunch.R_EARTH
+    b0, re = 3.12e-5, bunch.R_EARTH
+    g = float(bunch.gamma_of_kinetic(bunch.MEV))
+    um = C * math.sqrt(g * g - 1)
+    al = math.radians(30.0)
+    y = np.array([[r], [0.0], [0.0]])
+    u = np.array([[0.0], [um * math.sin(al)], [um * math.cos(al)]])
+    Beq = b0 * (re / r) ** 3
+    t = 0.0
+    worst_u = 0.0
+    bmax = 0.0
+    for _ in range(400):
+        y1, u1, t, _ = orc.transport(y, u, t, q=-QE, mass=ME, dt_max=1.0, frac=1 / 32, nsteps=250, ext_field=1,
+                                     b0=b0, re=re)
+        worst_u = max(worst_u, abs(np.linalg.norm(u1) / um - 1))
+        B = orc.dipole(b0, re, y1)[:, 0]
+        vpar = float(u1[:, 0] @ B)
+        bmax = max(bmax, float(np.linalg.norm(B)))
+        y, u = y1, u1
+        if vpar * float(np.array([0.0, um * math.sin(al), um * math.cos(al)]) @ orc.dipole(b0, re, np.array([[r], [0.0], [0.0]]))[:, 0]) < 0:
+            break
+    ratio = bmax / Beq
+    ok = worst_u < 1e-12 and abs(ratio / 4.0 - 1) < 0.01
+    return ok, f"|u| drift {worst_u:.1e}; mirror field / B_eq {ratio:.4f} (4 expected) at t = {t:.3e} s"
+
+
 ALL_PINS = [
     pin_constants, pin_uniform_retarded_time, pin_heaviside_feynman, pin_heaviside_feynman_far, pin_coulomb, pin_before_history_field,
     pin_bracket_bruteforce, pin_tie_goes_older, pin_circle_reconstruction_order, pin_circle_field_convergence,
     pin_larmor, pin_hc_gyration, pin_hc_exb_drift, pin_dipole, pin_step_history, pin_diag,
+    pin_transport_free_and_dt_rule, pin_transport_mirror,
 ]

@@ -2,7 +2,7 @@
 MUT_* switches in oracle/empp_oracle.c) and check that the pins catch it.
 This shows that the pins constrain every step of the oracle: the
 bracket rule, the root, the reconstruction, the LW formula, B, the pusher,
-the dipole and the history update."""
+the dipole, the history update and the Stage-II transport."""
 import pytest
 
 import oracle
@@ -21,6 +21,8 @@ MUTANTS = [
     "MUT_HC_TYPO",            # u- x t in the last HC step
     "MUT_NO_FINALISE",        # newest history velocity never finalised
     "MUT_ETA_ABSOLUTE",       # eta from the rounded absolute retarded position
+    "MUT_TRANSPORT_DT_NO_GAMMA",  # Stage-II step from 1/|B| without gamma
+    "MUT_TRANSPORT_OLD_V",    # Stage-II drift with the velocity before the kick
 ]
 
 
