@@ -261,6 +261,45 @@ empp_status empp_sync(empp_ctx *ctx);
 /* Change precision / search mode of an existing context.                 */
 empp_status empp_set_mode(empp_ctx *ctx, int32_t precision, int32_t guess);
 
+/* ---- two-stage strategy (Sec. 2.7) -----------------------------------------
+ * Stage I (empp_step) until the mean kinetic energy settles, then Stage II:
+ * no self-field, the particles move in the prescribed field alone.       */
+
+/* Stage I steps in windows of check_every steps until the growth rate of
+ * the mean kinetic energy over a window, |dE/dt| (J/s, from empp_diag's
+ * mean_kinetic), falls below eps_E, or max_steps are taken.  Outputs (any
+ * may be NULL): steps taken, the time reached, and whether the criterion
+ * was met.  Errors as empp_step; EINVAL on eps_E < 0 or check_every < 1. */
+empp_status empp_step_until_switch(empp_ctx *ctx, double eps_E, int64_t check_every, int64_t max_steps,
+                                   int64_t *steps_done, double *t_sw, int32_t *switched);
+
+/* Hand the present state over to Stage II: positions, proper velocities
+ * and time are kept, the history ring and self-fields are no longer used
+ * (empp_step, empp_fields_at and empp_get_history then return ESTATE;
+ * setting a history again returns to Stage I).  ESTATE before a history
+ * exists or after a handoff.                                              */
+empp_status empp_handoff(empp_ctx *ctx);
+
+/* Stage-II transport: nsteps steps with E = 0 and B = B_geo (the centred
+ * dipole, or 0 without an external field), Higuera-Cary and drift as in
+ * Stage I.  The step is
+ *   dt = min(dt_max, gyro_fraction * 2 pi m / |q| * min_i gamma_i / |B(y_i)|),
+ * a fraction of the shortest gyro-period in the bunch, re-evaluated on the
+ * device before every step (dt_max when nothing sees a field).  Blocks
+ * until done and advances the context's time.  ESTATE before the handoff;
+ * EINVAL on dt_max <= 0, gyro_fraction <= 0 or nsteps < 0.               */
+empp_status empp_transport(empp_ctx *ctx, double dt_max, double gyro_fraction, int64_t nsteps);
+
+/* Checkpoint: write the whole state (history ring in Stage I, or the
+ * Stage-II positions; proper velocities, slot times, the spatial order,
+ * step counters and clock) to a binary file at path, and read it back into
+ * a context created with the same n, depth, q, m and dt (EINVAL
+ * otherwise, or on an unreadable or truncated file, after which the
+ * context holds no state).  Caches (warm-start brackets, surrogate
+ * guesses) and the last step's fields are not saved.                     */
+empp_status empp_save(empp_ctx *ctx, const char *path);
+empp_status empp_load(empp_ctx *ctx, const char *path);
+
 #ifdef __cplusplus
 }
 #endif

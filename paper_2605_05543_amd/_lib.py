@@ -27,7 +27,8 @@ EXPORTS = [
     "empp_get_state", "empp_get_history", "empp_get_fields", "empp_get_diag", "empp_set_counting",
     "empp_get_counters", "empp_sync", "empp_set_mode", "empp_set_timing", "empp_get_timing",
     "empp_surrogate_set", "empp_surrogate_get", "empp_surrogate_samples", "empp_surrogate_samples_dev",
-    "empp_surrogate_forward", "empp_surrogate_loss_grad", "empp_surrogate_train",
+    "empp_surrogate_forward", "empp_surrogate_loss_grad", "empp_surrogate_train", "empp_step_until_switch",
+    "empp_handoff", "empp_transport", "empp_save", "empp_load",
 ]
 N_PARAMS = 18049
 
@@ -119,6 +120,12 @@ def _load():
         "empp_surrogate_forward": [_P, _P, _I64, _P],
         "empp_surrogate_loss_grad": [_P, _P, _P, _I64, ctypes.POINTER(_D), _P],
         "empp_surrogate_train": [_P, _P, _P, _I64, ctypes.POINTER(TrainCfg), ctypes.POINTER(TrainReport)],
+        "empp_step_until_switch": [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D),
+                                   ctypes.POINTER(_I32)],
+        "empp_handoff": [_P],
+        "empp_transport": [_P, _D, _D, _I64],
+        "empp_save": [_P, ctypes.c_char_p],
+        "empp_load": [_P, ctypes.c_char_p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -308,6 +315,29 @@ def empp_set_mode(h, precision, guess):
     _check(lib.empp_set_mode(h, int(precision), int(guess)))
 
 
+def empp_step_until_switch(h, eps_E, check_every, max_steps):
+    steps, t_sw, sw = _I64(), _D(), _I32()
+    _check(lib.empp_step_until_switch(h, float(eps_E), int(check_every), int(max_steps), ctypes.byref(steps),
+                                      ctypes.byref(t_sw), ctypes.byref(sw)))
+    return steps.value, t_sw.value, bool(sw.value)
+
+
+def empp_handoff(h):
+    _check(lib.empp_handoff(h))
+
+
+def empp_transport(h, dt_max, gyro_fraction, nsteps):
+    _check(lib.empp_transport(h, float(dt_max), float(gyro_fraction), int(nsteps)))
+
+
+def empp_save(h, path):
+    _check(lib.empp_save(h, os.fsencode(path)))
+
+
+def empp_load(h, path):
+    _check(lib.empp_load(h, os.fsencode(path)))
+
+
 class Context:
     """One empp_ctx.  Device memory comes from a torch tensor (PyTorch is
     the allocator and stream provider); kernels run on torch's current
@@ -429,3 +459,20 @@ class Context:
 
     def set_mode(self, precision, guess):
         empp_set_mode(self.h, precision, guess)
+
+    def step_until_switch(self, eps_E, check_every, max_steps):
+        """Stage I until |d(mean kinetic energy)/dt| < eps_E (J/s) over a
+        window of check_every steps: (steps taken, t_sw, switched)."""
+        return empp_step_until_switch(self.h, eps_E, check_every, max_steps)
+
+    def handoff(self):
+        empp_handoff(self.h)
+
+    def transport(self, dt_max, gyro_fraction, nsteps):
+        empp_transport(self.h, dt_max, gyro_fraction, nsteps)
+
+    def save(self, path):
+        empp_save(self.h, path)
+
+    def load(self, path):
+        empp_load(self.h, path)

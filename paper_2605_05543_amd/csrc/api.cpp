@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -31,6 +32,10 @@ hipError_t launch_ring_to_history(const double4 *rw, const double4 *rv, double *
                                   int head, hipStream_t s);
 hipError_t launch_newest_positions(const double4 *rw, double *r, int64_t N, int D, int head, hipStream_t s);
 hipError_t launch_diag(const double4 *rw, const double *u, int64_t N, int D, int head, double *out, hipStream_t s);
+hipError_t launch_handoff(const double4 *ring_w, int D, int head, double4 *pos, const double *u, int64_t N,
+                          double dip_k, int ext_field, unsigned long long *key, double *t, double t_now,
+                          hipStream_t s);
+hipError_t launch_transport(const TransportParams &p, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpPacked *net, const float *X, int64_t n, float *z, hipStream_t s);
 hipError_t launch_mlp_train(const MlpPacked *net, const float *X, const float *y, int64_t n, float scale,
                             float *part, int nblocks, hipStream_t s);
@@ -79,7 +84,7 @@ constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, order, kc, kc_bytes, total;
+    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, order, pos, skey, st, kc, kc_bytes, total;
 };
 
 int tile_for_depth(int D) { return pair_fp64_tile(D); }
@@ -166,6 +171,10 @@ Layout layout_for(const empp_config &c)
     L.counters = take(8 * sizeof(unsigned long long));
     L.diag = take(((N + kBlock - 1) / kBlock) * 7 * sizeof(double));
     L.order = take(N * sizeof(int32_t));
+    // Stage II: compact positions, the step-minimum slots and the clock
+    L.pos = take(N * sizeof(double4));
+    L.skey = take(4 * sizeof(unsigned long long));
+    L.st = take(sizeof(double));
     // previous-step brackets (warm start): uint16 per (source, target)
     L.kc_bytes = c.guess == EMPP_GUESS_PREVIOUS ? N * N * sizeof(uint16_t) : 0;
     L.kc = L.kc_bytes ? take(L.kc_bytes) : 0;
@@ -224,6 +233,7 @@ struct empp_ctx {
     bool have_bunch = false;
     bool have_history = false;
     bool handed_off = false;
+    int64_t tr_step = 0;    // Stage-II steps since the handoff
     bool counting = false;
     bool kc_valid = false;  // the bracket cache holds the previous step's brackets
     int head = 0;
@@ -262,6 +272,14 @@ struct empp_ctx {
     double *diag() const { return at<double>(L.diag); }
     int32_t *order() const { return at<int32_t>(L.order); }
     uint16_t *kc() const { return L.kc_bytes ? at<uint16_t>(L.kc) : nullptr; }
+    double4 *pos() const { return at<double4>(L.pos); }
+    unsigned long long *skey() const { return at<unsigned long long>(L.skey); }
+    double *stime() const { return at<double>(L.st); }
+    // present positions: the ring's newest slot (Stage I) or the compact
+    // array viewed as a one-slot ring (Stage II)
+    const double4 *present_pos() const { return handed_off ? pos() : ring_w(); }
+    int present_depth() const { return handed_off ? 1 : cfg.depth; }
+    int present_head() const { return handed_off ? 0 : head; }
 };
 
 namespace {
@@ -559,6 +577,7 @@ empp_status empp_init_history_straight(empp_ctx *ctx)
     ctx->step = 0;
     ctx->t_now = ctx->t_origin;  // t0 + 0 * dt
     ctx->have_history = true;
+    ctx->handed_off = false;
     ctx->kc_valid = false;
     ctx->handed_off = false;
     return EMPP_OK;
@@ -618,6 +637,7 @@ empp_status empp_set_history(empp_ctx *ctx, int32_t nslots, const double *T, con
     ctx->t_now = T[D - 1];
     ctx->have_bunch = true;
     ctx->have_history = true;
+    ctx->handed_off = false;
     ctx->kc_valid = false;
     ctx->handed_off = false;
     return EMPP_OK;
@@ -853,7 +873,8 @@ empp_status empp_get_state(empp_ctx *ctx, double *r, double *u, double *t, int64
     if (r) {
         double *tmp = nullptr;
         HIP_TRY(hipMalloc((void **)&tmp, 3 * N * sizeof(double)));
-        hipError_t e = launch_newest_positions(ctx->ring_w(), tmp, N, ctx->cfg.depth, ctx->head, ctx->stream);
+        hipError_t e = launch_newest_positions(ctx->present_pos(), tmp, N, ctx->present_depth(), ctx->present_head(),
+                                               ctx->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(r, tmp, 3 * N * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
         if (e == hipSuccess)
@@ -935,11 +956,13 @@ empp_status empp_get_diag(empp_ctx *ctx, empp_diag *out)
         return st;
     const int64_t N = ctx->cfg.n;
     const int64_t nb = (N + kBlock - 1) / kBlock;
-    HIP_TRY(launch_diag(ctx->ring_w(), ctx->u(), N, ctx->cfg.depth, ctx->head, ctx->diag(), ctx->stream));
+    HIP_TRY(launch_diag(ctx->present_pos(), ctx->u(), N, ctx->present_depth(), ctx->present_head(), ctx->diag(),
+                        ctx->stream));
     std::vector<double> h(nb * 7);
     double4 ref;
     HIP_TRY(hipMemcpyAsync(h.data(), ctx->diag(), nb * 7 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipMemcpyAsync(&ref, ctx->ring_w() + ctx->head, sizeof ref, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(&ref, ctx->present_pos() + ctx->present_head(), sizeof ref, hipMemcpyDeviceToHost,
+                           ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     double s[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int64_t b = 0; b < nb; ++b)
@@ -1301,6 +1324,256 @@ empp_status empp_set_mode(empp_ctx *ctx, int32_t precision, int32_t guess)
         return fail(EMPP_EUNSUPPORTED, "warm-start brackets need a context created with that guess mode");
     ctx->cfg.precision = precision;
     ctx->cfg.guess = guess;
+    return EMPP_OK;
+}
+
+
+// ---- two-stage strategy (Sec. 2.7) -----------------------------------------
+
+empp_status empp_step_until_switch(empp_ctx *ctx, double eps_E, int64_t check_every, int64_t max_steps,
+                                   int64_t *steps_done, double *t_sw, int32_t *switched)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    if (!(eps_E >= 0.0) || check_every < 1 || max_steps < 0)
+        return fail(EMPP_EINVAL, "need eps_E >= 0, check_every >= 1, max_steps >= 0");
+    empp_diag d0;
+    empp_status st = empp_get_diag(ctx, &d0);
+    if (st != EMPP_OK)
+        return st;
+    int64_t done = 0;
+    int32_t sw = 0;
+    double e_prev = d0.mean_kinetic, t_prev = d0.t;
+    while (done < max_steps) {
+        const int64_t k = std::min(check_every, max_steps - done);
+        if ((st = empp_step(ctx, k)) != EMPP_OK)
+            return st;
+        done += k;
+        empp_diag d;
+        if ((st = empp_get_diag(ctx, &d)) != EMPP_OK)
+            return st;
+        const double rate = (d.mean_kinetic - e_prev) / (d.t - t_prev);
+        e_prev = d.mean_kinetic;
+        t_prev = d.t;
+        if (std::fabs(rate) < eps_E) {
+            sw = 1;
+            break;
+        }
+    }
+    if (steps_done)
+        *steps_done = done;
+    if (t_sw)
+        *t_sw = ctx->t_now;
+    if (switched)
+        *switched = sw;
+    return EMPP_OK;
+}
+
+empp_status empp_handoff(empp_ctx *ctx)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    if (!ctx->have_history)
+        return fail(EMPP_ESTATE, "handoff before the history is initialised");
+    if (ctx->handed_off)
+        return fail(EMPP_ESTATE, "handoff already done");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    const double dip_k = ctx->cfg.dipole_b0 * ctx->cfg.dipole_re * ctx->cfg.dipole_re * ctx->cfg.dipole_re;
+    HIP_TRY(launch_handoff(ctx->ring_w(), ctx->cfg.depth, ctx->head, ctx->pos(), ctx->u(), ctx->cfg.n, dip_k,
+                           ctx->cfg.ext_field, ctx->skey(), ctx->stime(), ctx->t_now, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->handed_off = true;
+    ctx->tr_step = 0;
+    return EMPP_OK;
+}
+
+empp_status empp_transport(empp_ctx *ctx, double dt_max, double gyro_fraction, int64_t nsteps)
+{
+    if (!ctx)
+        return fail(EMPP_EINVAL, "NULL context");
+    if (!ctx->handed_off)
+        return fail(EMPP_ESTATE, "transport before handoff");
+    if (!(dt_max > 0.0) || !std::isfinite(dt_max) || !(gyro_fraction > 0.0) || nsteps < 0)
+        return fail(EMPP_EINVAL, "need dt_max > 0, gyro_fraction > 0, nsteps >= 0");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    TransportParams p{};
+    p.pos = ctx->pos();
+    p.u = ctx->u();
+    p.N = ctx->cfg.n;
+    p.q_over_2m = ctx->cfg.q / (2.0 * ctx->cfg.m);
+    p.dip_k = ctx->cfg.dipole_b0 * ctx->cfg.dipole_re * ctx->cfg.dipole_re * ctx->cfg.dipole_re;
+    p.ext_field = ctx->cfg.ext_field;
+    p.dt_max = dt_max;
+    p.gyro_k = ctx->cfg.q != 0.0 ? gyro_fraction * 2.0 * M_PI * ctx->cfg.m / std::fabs(ctx->cfg.q) : INFINITY;
+    p.key = ctx->skey();
+    p.t = ctx->stime();
+    for (int64_t k = 0; k < nsteps; ++k) {
+        p.step = ctx->tr_step++;
+        HIP_TRY(timed(ctx, 1, [&]() { return launch_transport(p, ctx->stream); }));
+    }
+    double t = 0.0;
+    HIP_TRY(hipMemcpyAsync(&t, ctx->stime(), sizeof t, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->t_now = t;
+    ctx->step += nsteps;
+    return EMPP_OK;
+}
+
+// ---- checkpoint --------------------------------------------------------------
+
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int64_t n;
+    int32_t depth, head;
+    int64_t step, tr_step;
+    double t_now, t_origin;
+    int32_t stage, reserved;
+    double q, m, dt;
+};
+constexpr char kCkptMagic[8] = {'E', 'M', 'P', 'P', 'C', 'K', 'P', '1'};
+
+// Device <-> file through a bounded host buffer.
+empp_status dev_to_file(empp_ctx *ctx, FILE *f, const void *dev, uint64_t bytes)
+{
+    std::vector<char> buf((size_t)std::min<uint64_t>(bytes, 64ull << 20));
+    for (uint64_t o = 0; o < bytes; o += buf.size()) {
+        size_t k = (size_t)std::min<uint64_t>(buf.size(), bytes - o);
+        HIP_TRY(hipMemcpyAsync(buf.data(), (const char *)dev + o, k, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        if (fwrite(buf.data(), 1, k, f) != k)
+            return fail(EMPP_EINVAL, "checkpoint write failed: %s", strerror(errno));
+    }
+    return EMPP_OK;
+}
+
+empp_status file_to_dev(empp_ctx *ctx, FILE *f, void *dev, uint64_t bytes)
+{
+    std::vector<char> buf((size_t)std::min<uint64_t>(bytes, 64ull << 20));
+    for (uint64_t o = 0; o < bytes; o += buf.size()) {
+        size_t k = (size_t)std::min<uint64_t>(buf.size(), bytes - o);
+        if (fread(buf.data(), 1, k, f) != k)
+            return fail(EMPP_EINVAL, "checkpoint truncated");
+        HIP_TRY(hipMemcpyAsync((char *)dev + o, buf.data(), k, hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    return EMPP_OK;
+}
+}  // namespace
+
+empp_status empp_save(empp_ctx *ctx, const char *path)
+{
+    if (!ctx || !path)
+        return fail(EMPP_EINVAL, "NULL argument");
+    if (!ctx->have_history)
+        return fail(EMPP_ESTATE, "nothing to save before the history is initialised");
+    empp_status st = empp_sync(ctx);
+    if (st != EMPP_OK)
+        return st;
+    FILE *f = fopen(path, "wb");
+    if (!f)
+        return fail(EMPP_EINVAL, "cannot open %s: %s", path, strerror(errno));
+    const int64_t N = ctx->cfg.n;
+    const int D = ctx->cfg.depth;
+    CkptHeader h{};
+    memcpy(h.magic, kCkptMagic, 8);
+    h.n = N;
+    h.depth = D;
+    h.head = ctx->head;
+    h.step = ctx->step;
+    h.tr_step = ctx->tr_step;
+    h.t_now = ctx->t_now;
+    h.t_origin = ctx->t_origin;
+    h.stage = ctx->handed_off ? 2 : 1;
+    h.q = ctx->cfg.q;
+    h.m = ctx->cfg.m;
+    h.dt = ctx->cfg.dt;
+    if (fwrite(&h, sizeof h, 1, f) != 1)
+        st = fail(EMPP_EINVAL, "checkpoint write failed: %s", strerror(errno));
+    if (st == EMPP_OK)
+        st = dev_to_file(ctx, f, ctx->T(), D * sizeof(double));
+    if (st == EMPP_OK)
+        st = dev_to_file(ctx, f, ctx->u(), 3 * N * sizeof(double));
+    if (st == EMPP_OK)
+        st = dev_to_file(ctx, f, ctx->order(), N * sizeof(int32_t));
+    if (st == EMPP_OK && h.stage == 1) {
+        st = dev_to_file(ctx, f, ctx->ring_w(), (uint64_t)N * D * sizeof(double4));
+        if (st == EMPP_OK)
+            st = dev_to_file(ctx, f, ctx->ring_v(), (uint64_t)N * D * sizeof(double4));
+    }
+    if (st == EMPP_OK && h.stage == 2) {
+        st = dev_to_file(ctx, f, ctx->pos(), N * sizeof(double4));
+        if (st == EMPP_OK)
+            st = dev_to_file(ctx, f, ctx->skey(), 3 * sizeof(unsigned long long));
+        if (st == EMPP_OK)
+            st = dev_to_file(ctx, f, ctx->stime(), sizeof(double));
+    }
+    if (fclose(f) != 0 && st == EMPP_OK)
+        st = fail(EMPP_EINVAL, "checkpoint close failed: %s", strerror(errno));
+    return st;
+}
+
+empp_status empp_load(empp_ctx *ctx, const char *path)
+{
+    if (!ctx || !path)
+        return fail(EMPP_EINVAL, "NULL argument");
+    empp_status st = set_device(ctx);
+    if (st != EMPP_OK)
+        return st;
+    FILE *f = fopen(path, "rb");
+    if (!f)
+        return fail(EMPP_EINVAL, "cannot open %s: %s", path, strerror(errno));
+    CkptHeader h{};
+    const int64_t N = ctx->cfg.n;
+    const int D = ctx->cfg.depth;
+    if (fread(&h, sizeof h, 1, f) != 1 || memcmp(h.magic, kCkptMagic, 8) != 0)
+        st = fail(EMPP_EINVAL, "%s is not a checkpoint", path);
+    else if (h.n != N || h.depth != D || h.q != ctx->cfg.q || h.m != ctx->cfg.m || h.dt != ctx->cfg.dt)
+        st = fail(EMPP_EINVAL, "checkpoint (n %lld, depth %d, q, m, dt) does not match the context",
+                  (long long)h.n, h.depth);
+    else if ((h.stage != 1 && h.stage != 2) || h.head < 0 || h.head >= D)
+        st = fail(EMPP_EINVAL, "corrupt checkpoint header");
+    if (st == EMPP_OK)
+        st = file_to_dev(ctx, f, ctx->T(), D * sizeof(double));
+    if (st == EMPP_OK)
+        st = file_to_dev(ctx, f, ctx->u(), 3 * N * sizeof(double));
+    if (st == EMPP_OK)
+        st = file_to_dev(ctx, f, ctx->order(), N * sizeof(int32_t));
+    if (st == EMPP_OK && h.stage == 1) {
+        st = file_to_dev(ctx, f, ctx->ring_w(), (uint64_t)N * D * sizeof(double4));
+        if (st == EMPP_OK)
+            st = file_to_dev(ctx, f, ctx->ring_v(), (uint64_t)N * D * sizeof(double4));
+    }
+    if (st == EMPP_OK && h.stage == 2) {
+        st = file_to_dev(ctx, f, ctx->pos(), N * sizeof(double4));
+        if (st == EMPP_OK)
+            st = file_to_dev(ctx, f, ctx->skey(), 3 * sizeof(unsigned long long));
+        if (st == EMPP_OK)
+            st = file_to_dev(ctx, f, ctx->stime(), sizeof(double));
+    }
+    fclose(f);
+    if (st != EMPP_OK) {
+        // the device state is partly overwritten: nothing valid remains
+        ctx->have_history = false;
+        ctx->handed_off = false;
+        return st;
+    }
+    HIP_TRY(hipMemsetAsync(ctx->E(), 0, 3 * N * sizeof(double), ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->B(), 0, 3 * N * sizeof(double), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->have_bunch = false;
+    ctx->have_history = true;
+    ctx->handed_off = h.stage == 2;
+    ctx->kc_valid = false;
+    ctx->head = h.head;
+    ctx->step = h.step;
+    ctx->tr_step = h.tr_step;
+    ctx->t_now = h.t_now;
+    ctx->t_origin = h.t_origin;
     return EMPP_OK;
 }
 

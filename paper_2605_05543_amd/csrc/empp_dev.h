@@ -109,6 +109,28 @@ __device__ inline void pair_block_coords(int nbx, int nsplit, int &bx, int &spli
     }
 }
 
+// Stage II (transport after the handoff): positions pos[i] = {x, y, z, 0},
+// proper velocities u[3][N]; the step is
+// dt = min(dt_max, gyro_k * min_i gamma_i / |B(y_i)|), the minimum being
+// kept in three rotating slots of double bit patterns (positive doubles
+// order like their unsigned bit patterns): step k reads slot k % 3, builds
+// slot (k + 1) % 3 with atomicMin and clears slot (k + 2) % 3.
+struct TransportParams {
+    double4 *pos;
+    double *u;
+    int64_t N;
+    double q_over_2m;
+    double dip_k;
+    int32_t ext_field;
+    double dt_max;
+    double gyro_k;
+    unsigned long long *key;  // [3]
+    double *t;                // [1] present time
+    int64_t step;
+};
+
+constexpr unsigned long long kPosInfBits = 0x7FF0000000000000ull;
+
 // Error word: err[0] = (target << 32 | source) of the lowest failing pair
 // (atomicMin), err[1] = OR of status bits.
 constexpr unsigned long long kErrCoincident = 1ull;

@@ -238,6 +238,123 @@ __global__ void diag_kernel(const double4 *ring_w, const double *u, int64_t N, i
             out[blockIdx.x * 7 + k] = red[k][0];
 }
 
+// ---- Stage II: prescribed field only (Sec. 2.7) ---------------------------
+
+// gamma / |B| of one particle, +inf where it sees no field.
+__device__ inline double gyro_key(double4 y, double ux, double uy, double uz, double dip_k, int ext_field)
+{
+    if (ext_field != 1)
+        return __longlong_as_double((long long)kPosInfBits);
+    double bx, by, bz;
+    dipole_field(y.x, y.y, y.z, dip_k, bx, by, bz);
+    const double c = kC_LIGHT;
+    double g = sqrt(1.0 + (ux * ux + uy * uy + uz * uz) / (c * c));
+    double bm = sqrt(bx * bx + by * by + bz * bz);
+    return bm > 0.0 ? g / bm : __longlong_as_double((long long)kPosInfBits);
+}
+
+// Block minimum of a positive double, folded into *slot with one atomic.
+__device__ inline void block_min_to(double v, unsigned long long *slot)
+{
+    __shared__ double wmin[16];
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmin(v, __shfl_xor(v, off));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        wmin[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = wmin[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
+            m = fmin(m, wmin[k]);
+        atomicMin(slot, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// Positions of the newest slot -> compact Stage-II array; clears the three
+// step slots and sets the clock.
+__global__ void handoff_kernel(const double4 *ring_w, int D, int head, double4 *pos, int64_t N,
+                               unsigned long long *key, double *t, double t_now)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+        double4 y = ring_w[i * D + head];
+        pos[i] = make_double4(y.x, y.y, y.z, 0.0);
+    }
+    if (i == 0) {
+        key[0] = key[1] = key[2] = kPosInfBits;
+        t[0] = t_now;
+    }
+}
+
+// The first step's minimum (slot 0) from the handed-off state.
+__global__ void transport_key_kernel(const double4 *pos, const double *u, int64_t N, double dip_k, int ext_field,
+                                     unsigned long long *key)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double k = __longlong_as_double((long long)kPosInfBits);
+    if (i < N)
+        k = gyro_key(pos[i], u[i], u[N + i], u[2 * N + i], dip_k, ext_field);
+    block_min_to(k, key);
+}
+
+// One Stage-II step: E = 0, B = B_geo, Higuera-Cary, drift with the new
+// velocity; then the next step's gamma / |B| at the new state.
+__global__ void transport_kernel(TransportParams p)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int s0 = (int)(p.step % 3);
+    const int s1 = s0 == 2 ? 0 : s0 + 1;
+    const int s2 = s1 == 2 ? 0 : s1 + 1;
+    const double kmin = __longlong_as_double((long long)p.key[s0]);
+    double dt = p.dt_max;
+    const double d = p.gyro_k * kmin;
+    if (d < dt)
+        dt = d;
+    double knext = __longlong_as_double((long long)kPosInfBits);
+    if (i < p.N) {
+        double4 y = p.pos[i];
+        double bx = 0.0, by = 0.0, bz = 0.0;
+        if (p.ext_field == 1)
+            dipole_field(y.x, y.y, y.z, p.dip_k, bx, by, bz);
+        double ux = p.u[i], uy = p.u[p.N + i], uz = p.u[2 * p.N + i];
+        higuera_cary(ux, uy, uz, 0.0, 0.0, 0.0, bx, by, bz, p.q_over_2m * dt);
+        const double c = kC_LIGHT;
+        double ig = 1.0 / sqrt(1.0 + (ux * ux + uy * uy + uz * uz) / (c * c));
+        y = make_double4(y.x + ux * ig * dt, y.y + uy * ig * dt, y.z + uz * ig * dt, 0.0);
+        p.pos[i] = y;
+        p.u[i] = ux;
+        p.u[p.N + i] = uy;
+        p.u[2 * p.N + i] = uz;
+        knext = gyro_key(y, ux, uy, uz, p.dip_k, p.ext_field);
+    }
+    block_min_to(knext, p.key + s1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        p.key[s2] = kPosInfBits;
+        p.t[0] += dt;
+    }
+}
+
+hipError_t launch_handoff(const double4 *ring_w, int D, int head, double4 *pos, const double *u, int64_t N,
+                          double dip_k, int ext_field, unsigned long long *key, double *t, double t_now,
+                          hipStream_t s)
+{
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(handoff_kernel, dim3(nb), dim3(256), 0, s, ring_w, D, head, pos, N, key, t, t_now);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(transport_key_kernel, dim3(nb), dim3(256), 0, s, (const double4 *)pos, u, N, dip_k,
+                       ext_field, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_transport(const TransportParams &p, hipStream_t s)
+{
+    hipLaunchKernelGGL(transport_kernel, dim3((unsigned)((p.N + 255) / 256)), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, double *E, double *B, hipStream_t s)
 {
     hipLaunchKernelGGL(merge_fields_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, part, nsplit, m,

@@ -1,0 +1,207 @@
+"""Two-stage strategy (Sec. 2.7) and checkpoints through the C ABI.
+
+Stage II on the GPU against the oracle's Stage II from the same state; the
+switching monitor against the diagnostics it reads; handoff state rules;
+save/load round trips that must continue bit for bit."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_05543_amd import bunch
+
+pytestmark = pytest.mark.gpu
+
+Q, ME, C = -bunch.E_CHARGE, bunch.M_ELECTRON, bunch.C_LIGHT
+B0, RE = 3.12e-5, bunch.R_EARTH
+
+
+def _ctx(n, depth, dt, **kw):
+    from paper_2605_05543_amd._lib import Context
+
+    return Context(n=n, depth=depth, q=Q, m=ME, dt=dt, **kw)
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.get()
+
+
+def _dipole_bunch(n, seed, pitch_deg=30.0):
+    """1 MeV electrons 1 mm around (3 R_E, 0, 0) with the given pitch angle
+    to the local (equatorial, along -z) field."""
+    rng = np.random.default_rng(seed)
+    r = 1e-3 * rng.standard_normal((3, n))
+    r[0] += 3 * RE
+    g = float(bunch.gamma_of_kinetic(bunch.MEV))
+    um = C * math.sqrt(g * g - 1)
+    al = math.radians(pitch_deg) + 1e-3 * rng.standard_normal(n)
+    u = np.stack([np.zeros(n), um * np.sin(al), um * np.cos(al)])
+    return r, u
+
+
+@pytest.mark.parametrize("dt_max,frac,nsteps", [(1e-7, 1 / 32, 600), (1.0, 1 / 32, 600), (1.0, 1 / 8, 300)])
+def test_transport_matches_oracle(orc, dt_max, frac, nsteps):
+    """Handoff straight after the history is built, then Stage II in the
+    dipole: positions to 1e-12 of the distance travelled, |u| to 1e-13,
+    the clock to 1e-12 (the step is chosen from the same minimum on both
+    sides)."""
+    print(f"case transport dt_max={dt_max} frac={frac} steps={nsteps}", flush=True)
+    n = 96
+    r, u = _dipole_bunch(n, 5)
+    with _ctx(n, 8, 1e-13, ext_field=1, dipole_b0=B0, dipole_re=RE) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        ctx.handoff()
+        ctx.transport(dt_max, frac, nsteps)
+        rg, ug, tg, _ = ctx.state()
+    ro, uo, to, _ = orc.transport(r, u, 0.0, q=Q, mass=ME, dt_max=dt_max, frac=frac, nsteps=nsteps, ext_field=1,
+                                  b0=B0, re=RE)
+    travel = np.max(np.linalg.norm(ro - r, axis=0))
+    dy = np.max(np.linalg.norm(rg - ro, axis=0)) / travel
+    du = np.max(np.abs(np.linalg.norm(ug, axis=0) / np.linalg.norm(u, axis=0) - 1))
+    dth = np.max(np.linalg.norm(ug - uo, axis=0) / np.linalg.norm(uo, axis=0))
+    print(f"   travelled {travel:.3e} m in {to:.3e} s; GPU vs oracle: position {dy:.2e} of it, "
+          f"u direction {dth:.2e}, |u| drift {du:.2e}, clock {abs(tg / to - 1):.2e}", flush=True)
+    assert dy < 1e-12 and dth < 1e-10 and du < 1e-13 and abs(tg / to - 1) < 1e-12
+
+
+def test_stage_one_then_transport(orc):
+    """C1-like bunch: Stage I on both sides for 30 steps from the same
+    initial state, handoff, Stage II without a field (free streaming at
+    dt_max); the two runs agree to rounding."""
+    print("case stage I + handoff + free transport", flush=True)
+    wl = bunch.C1
+    n = 64
+    spec = bunch.BunchSpec(n, (1e-3, 1e-3, 1e-3), 1.0, seed=9)
+    r, u = bunch.gaussian_bunch(spec)
+    run = oracle.OracleRun(orc, r, u, D=32, dt=wl.dt, q=Q, mass=ME)
+    run.step(30)
+    yo, uo, to, _ = orc.transport(run.y, run.u, run.t, q=Q, mass=ME, dt_max=1e-12, frac=0.05, nsteps=50)
+    with _ctx(n, 32, wl.dt) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        ctx.step(30)
+        ctx.handoff()
+        ctx.transport(1e-12, 0.05, 50)
+        rg, ug, tg, sg = ctx.state()
+        d = ctx.diag()
+    dy = np.max(np.abs(rg - yo)) / np.std(r)
+    du = np.max(np.abs(ug - uo)) / np.max(np.abs(uo))
+    print(f"   max|dy|/sigma {dy:.2e}, max|du|/|u| {du:.2e}, t {tg} vs {to}", flush=True)
+    assert dy < 1e-12 and du < 1e-13 and abs(tg - to) < 1e-24 and sg == 80
+    od = orc.diag(yo, uo, ME)
+    assert abs(d["sigma"][0] / od[0] - 1) < 1e-9 and abs(d["mean_kinetic"] / od[7] - 1) < 1e-12
+
+
+def test_handoff_state_rules():
+    from paper_2605_05543_amd._lib import EMPP_ESTATE, EmppError
+
+    print("case handoff state rules", flush=True)
+    r, u = _dipole_bunch(16, 3)
+    with _ctx(16, 8, 1e-13, ext_field=1, dipole_b0=B0, dipole_re=RE) as ctx:
+        with pytest.raises(EmppError) as ei:
+            ctx.handoff()
+        assert ei.value.status == EMPP_ESTATE
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        with pytest.raises(EmppError) as ei:
+            ctx.transport(1e-7, 0.03, 1)
+        assert ei.value.status == EMPP_ESTATE
+        ctx.handoff()
+        for call in (lambda: ctx.step(1), lambda: ctx.fields_at(0.0, r), lambda: ctx.history(), ctx.handoff):
+            with pytest.raises(EmppError) as ei:
+                call()
+            assert ei.value.status == EMPP_ESTATE
+        ctx.transport(1e-7, 0.03, 3)
+        ctx.init_history_straight()  # back to Stage I
+        ctx.step(1)
+
+
+def test_step_until_switch():
+    """The monitor stops at the first window whose mean-energy growth rate
+    is below the threshold: checked against the diagnostics of a second
+    context that takes the same steps window by window."""
+    print("case switching criterion", flush=True)
+    n, depth, dt = 128, 64, 1e-13
+    spec = bunch.BunchSpec(n, (0.2e-3, 0.2e-3, 0.2e-3), 1.0, seed=12)
+    r, u = bunch.gaussian_bunch(spec)
+    rates = []
+    with _ctx(n, depth, dt) as ref:
+        ref.init_bunch(r, u, 0.0)
+        ref.init_history_straight()
+        d = ref.diag()
+        e0, t0 = d["mean_kinetic"], d["t"]
+        for _ in range(12):
+            ref.step(10)
+            d = ref.diag()
+            rates.append(abs((d["mean_kinetic"] - e0) / (d["t"] - t0)))
+            e0, t0 = d["mean_kinetic"], d["t"]
+    eps = 0.5 * (max(rates) + min(rates))
+    want = next(k for k, x in enumerate(rates) if x < eps) + 1
+    with _ctx(n, depth, dt) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        steps, t_sw, sw = ctx.step_until_switch(eps, 10, 120)
+        assert sw and steps == 10 * want and t_sw == ctx.state()[2]
+        ctx.init_history_straight()
+        steps, t_sw, sw = ctx.step_until_switch(0.0, 10, 35)
+        assert not sw and steps == 35
+    print(f"   window rates {np.array(rates)} J/s; eps {eps:.3e}: switched after {10 * want} steps", flush=True)
+
+
+@pytest.mark.parametrize("stage", [1, 2])
+def test_save_load_continues_bit_for_bit(tmp_path, stage):
+    print(f"case checkpoint stage {stage}", flush=True)
+    n, depth, dt = 64, 32, 1e-13
+    r, u = _dipole_bunch(n, 8)
+    kw = dict(ext_field=1, dipole_b0=B0, dipole_re=RE)
+    path = str(tmp_path / "ckpt.bin")
+    with _ctx(n, depth, dt, **kw) as a:
+        a.init_bunch(r, u, 0.0)
+        a.init_history_straight()
+        a.step(10)
+        if stage == 2:
+            a.handoff()
+            a.transport(1e-7, 1 / 32, 5)
+        a.save(path)
+        if stage == 1:
+            a.step(7)
+        else:
+            a.transport(1e-7, 1 / 32, 7)
+        ra, ua, ta, sa = a.state()
+    with _ctx(n, depth, dt, **kw) as b:
+        b.load(path)
+        if stage == 1:
+            b.step(7)
+        else:
+            b.transport(1e-7, 1 / 32, 7)
+        rb, ub, tb, sb = b.state()
+    assert np.array_equal(ra, rb) and np.array_equal(ua, ub) and ta == tb and sa == sb
+
+
+def test_load_rejects_mismatch(tmp_path):
+    from paper_2605_05543_amd._lib import EMPP_EINVAL, EMPP_ESTATE, EmppError
+
+    print("case checkpoint mismatch", flush=True)
+    r, u = _dipole_bunch(16, 1)
+    path = str(tmp_path / "c.bin")
+    with _ctx(16, 8, 1e-13) as a:
+        a.init_bunch(r, u, 0.0)
+        a.init_history_straight()
+        a.save(path)
+    with _ctx(16, 16, 1e-13) as b:
+        with pytest.raises(EmppError) as ei:
+            b.load(path)
+        assert ei.value.status == EMPP_EINVAL
+        with pytest.raises(EmppError) as ei:
+            b.step(1)
+        assert ei.value.status == EMPP_ESTATE
+    bad = str(tmp_path / "bad.bin")
+    with open(bad, "wb") as f:
+        f.write(b"not a checkpoint at all")
+    with _ctx(16, 8, 1e-13) as c:
+        with pytest.raises(EmppError) as ei:
+            c.load(bad)
+        assert ei.value.status == EMPP_EINVAL
