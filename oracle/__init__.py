@@ -85,6 +85,13 @@ class Oracle:
         L.oracle_diag.restype = None
         L.oracle_transport.argtypes = [_I64, _D, _D, _I32, _D, _D, _D, _D, _P, _P, _P, _I64, _P]
         L.oracle_transport.restype = ctypes.c_int
+        L.oracle_adaptive_scan.argtypes = [_I64, _I32, _P, _P, _P, _D, _I64, _P, _P, _P, _D, _P]
+        L.oracle_adaptive_scan.restype = ctypes.c_int
+        L.oracle_adaptive_dt.argtypes = [_D, _D, _D, _D, _D]
+        L.oracle_adaptive_dt.restype = ctypes.c_double
+        L.oracle_step_adaptive.argtypes = [_I64, _I32, _D, _D, _D, _D, _D, _D, _I32, _D, _D, _P, _P, _P, _P, _P,
+                                           _I64, ctypes.c_int, _P]
+        L.oracle_step_adaptive.restype = ctypes.c_int
         L.oracle_max_threads.argtypes = []
         self.L = L
         c = np.zeros(6)
@@ -168,6 +175,37 @@ class Oracle:
         if st != OR_OK:
             raise OracleError(st)
         return y, u, float(tt[0]), float(dl[0])
+
+    def adaptive_scan(self, T, w, v, t, x, self_index, vt, eta_allow):
+        """Sec. 2.4: (eta_min, v_max) over the pairs of targets x[3][m] with
+        present velocities vt[3][m] against the history."""
+        T, w, v, x, vt = _f64(T), _f64(w), _f64(v), _f64(x), _f64(vt)
+        si = None if self_index is None else np.ascontiguousarray(self_index, dtype=np.int64)
+        out = np.zeros(2)
+        st = self.L.oracle_adaptive_scan(w.shape[2], len(T), _ptr(T), _ptr(w), _ptr(v), float(t), x.shape[1],
+                                         _ptr(x), _ptr(si), _ptr(vt), float(eta_allow), _ptr(out))
+        if st != OR_OK:
+            raise OracleError(st)
+        return float(out[0]), float(out[1])
+
+    def adaptive_dt(self, eta_min, v_max, c_dt=0.05, dt_min=1e-15, dt_max=1e-12):
+        return float(self.L.oracle_adaptive_dt(float(eta_min), float(v_max), float(c_dt), float(dt_min),
+                                               float(dt_max)))
+
+    def step_adaptive(self, T, w, v, u, nsteps, *, q, mass, c_dt=0.05, dt_min=1e-15, dt_max=1e-12, eta_allow=0.0,
+                      ext_field=0, b0=0.0, re=0.0, nthreads=None):
+        """Adaptive-step EM-PP (in place on copies): returns (T, w, v, u, dts)."""
+        T, w, v, u = _f64(T).copy(), _f64(w).copy(), _f64(v).copy(), _f64(u).copy()
+        dts = np.zeros(max(int(nsteps), 1))
+        bad = np.zeros(2, dtype=np.int64)
+        nt = nthreads or self.L.oracle_max_threads()
+        st = self.L.oracle_step_adaptive(w.shape[2], len(T), float(q), float(mass), float(c_dt), float(dt_min),
+                                         float(dt_max), float(eta_allow), int(ext_field), float(b0), float(re),
+                                         _ptr(T), _ptr(w), _ptr(v), _ptr(u), _ptr(dts), int(nsteps), int(nt),
+                                         _ptr(bad))
+        if st != OR_OK:
+            raise OracleError(st)
+        return T, w, v, u, dts[:nsteps]
 
     def diag(self, y, u, mass):
         out = np.zeros(8)

@@ -617,6 +617,126 @@ int oracle_step(int64_t N, int32_t D, double q, double mass, double dt, double t
     return st;
 }
 
+/* Sec. 2.4 adaptive step.  From the same per-pair retarded quantities as
+ * the field sum, over the pairs i != j with |eta_ij| >= eta_allow:
+ *   eta_min = min |eta_ij|,   v_max = max |v_i(t) - v_j(t_r,ij)|,
+ * with v_i(t) the target's present velocity vt[3][m] and v_j(t_r) the
+ * reconstructed retarded velocity.  out = {eta_min, v_max}; eta_min = +inf
+ * and v_max = 0 when no pair qualifies.                                    */
+int oracle_adaptive_scan(int64_t N, int32_t ns, const double *T, const double *w, const double *v,
+                         double t, int64_t m, const double *x, const int64_t *self_index,
+                         const double *vt, double eta_allow, double out[2])
+{
+    if (N < 1 || ns < 2 || m < 0 || t != T[ns - 1])
+        return OR_EINVAL;
+    double emin = INFINITY, vmax = 0.0;
+    for (int64_t a = 0; a < m; ++a) {
+        double r[3] = {x[a], x[m + a], x[2 * m + a]};
+        double va[3] = {vt[a], vt[m + a], vt[2 * m + a]};
+        for (int64_t j = 0; j < N; ++j) {
+            if (self_index && self_index[a] == j)
+                continue;
+            retarded_t rt;
+            int st = solve_retarded(N, ns, T, w, v, j, r, t, &rt);
+            if (st != OR_OK)
+                return st;
+            double en = sqrt(dot3(rt.eta, rt.eta));
+#ifdef MUT_ADAPT_ETA_PRESENT
+            double wn[3];
+            load_sample(w, N, ns - 1, j, wn);
+            double dn[3] = {r[0] - wn[0], r[1] - wn[1], r[2] - wn[2]};
+            en = sqrt(dot3(dn, dn));
+#endif
+#ifndef MUT_ADAPT_NO_ALLOW
+            if (en < eta_allow)
+                continue;
+#endif
+            double dv[3] = {va[0] - rt.vr[0], va[1] - rt.vr[1], va[2] - rt.vr[2]};
+            double sp = sqrt(dot3(dv, dv));
+            if (en < emin)
+                emin = en;
+            if (sp > vmax)
+                vmax = sp;
+        }
+    }
+    out[0] = emin;
+    out[1] = vmax;
+    return OR_OK;
+}
+
+/* dt = C_dt eta_min / v_max, then clamped to [dt_min, dt_max]; dt_max when
+ * no pair qualified or nothing moves relative to anything.               */
+double oracle_adaptive_dt(double eta_min, double v_max, double c_dt, double dt_min, double dt_max)
+{
+    if (!(v_max > 0.0) || !(eta_min < INFINITY))
+        return dt_max;
+    double dt = c_dt * eta_min / v_max;
+    return fmin(dt_max, fmax(dt_min, dt));
+}
+
+/* EM-PP steps with the adaptive step of Sec. 2.4: as oracle_step, with the
+ * step of every pass taken from oracle_adaptive_scan at the present state
+ * (targets: the particles, present velocities: the newest slot's) and the
+ * new slot at T_{n+1} = T_n + dt.  dts[k] receives the k-th step.          */
+int oracle_step_adaptive(int64_t N, int32_t D, double q, double mass, double c_dt, double dt_min,
+                         double dt_max, double eta_allow, int32_t ext_field, double b0, double re,
+                         double *T, double *w, double *v, double *u, double *dts, int64_t nsteps,
+                         int nthreads, int64_t *bad)
+{
+    if (N < 2 || D < 2 || nsteps < 0 || !(dt_min > 0.0) || !(dt_max >= dt_min))
+        return OR_EINVAL;
+    double *y = (double *)malloc(sizeof(double) * 3 * N);
+    double *E = (double *)malloc(sizeof(double) * 3 * N);
+    double *B = (double *)malloc(sizeof(double) * 3 * N);
+    double *Bg = (double *)malloc(sizeof(double) * 3 * N);
+    double *vt = (double *)malloc(sizeof(double) * 3 * N);
+    double *vnew = (double *)malloc(sizeof(double) * 3 * N);
+    int64_t *self = (int64_t *)malloc(sizeof(int64_t) * N);
+    int st = OR_OK;
+    if (!y || !E || !B || !Bg || !vt || !vnew || !self)
+        st = OR_EINVAL;
+    for (int64_t i = 0; st == OR_OK && i < N; ++i)
+        self[i] = i;
+    for (int64_t step = 0; st == OR_OK && step < nsteps; ++step) {
+        double t = T[D - 1];
+        memcpy(y, w + (int64_t)(D - 1) * 3 * N, sizeof(double) * 3 * N);
+        memcpy(vt, v + (int64_t)(D - 1) * 3 * N, sizeof(double) * 3 * N);
+        st = oracle_fields(N, D, T, w, v, q, t, N, y, self, E, B, NULL, nthreads, bad);
+        if (st != OR_OK)
+            break;
+        double ev[2];
+        st = oracle_adaptive_scan(N, D, T, w, v, t, N, y, self, vt, eta_allow, ev);
+        if (st != OR_OK)
+            break;
+        double dt = oracle_adaptive_dt(ev[0], ev[1], c_dt, dt_min, dt_max);
+        if (dts)
+            dts[step] = dt;
+        if (ext_field == 1) {
+            oracle_dipole(b0, re, N, y, Bg);
+            for (int64_t p = 0; p < 3 * N; ++p)
+                B[p] += Bg[p];
+        }
+        oracle_hc(q, mass, dt, N, u, E, B);
+        for (int64_t i = 0; i < N; ++i) {
+            double ui[3] = {u[i], u[N + i], u[2 * N + i]}, vi[3];
+            velocity_of(ui, vi);
+            for (int c = 0; c < 3; ++c)
+                vnew[c * N + i] = vi[c];
+        }
+        memcpy(v + (int64_t)(D - 1) * 3 * N, vnew, sizeof(double) * 3 * N);
+        memmove(T, T + 1, sizeof(double) * (D - 1));
+        memmove(w, w + 3 * N, sizeof(double) * 3 * N * (D - 1));
+        memmove(v, v + 3 * N, sizeof(double) * 3 * N * (D - 1));
+        T[D - 1] = t + dt;
+        for (int64_t p = 0; p < 3 * N; ++p) {
+            w[(int64_t)(D - 1) * 3 * N + p] = y[p] + vnew[p] * dt;
+            v[(int64_t)(D - 1) * 3 * N + p] = vnew[p];
+        }
+    }
+    free(y); free(E); free(B); free(Bg); free(vt); free(vnew); free(self);
+    return st;
+}
+
 /* Stage II of Sec. 2.7: after the switch the self-field is dropped and the
  * particles move in the prescribed field alone, E = 0 and B = B_geo(y)
  * (Sec. 2.6; B = 0 without an external field), advanced by the same

@@ -17,6 +17,7 @@ import math
 
 import numpy as np
 
+import oracle
 from paper_2605_05543_amd import bunch
 
 # CODATA 2018, written here independently of the oracle.
@@ -577,9 +578,60 @@ def pin_transport_mirror(orc):
     return ok, f"|u| drift {worst_u:.1e}; mirror field / B_eq {ratio:.4f} (4 expected) at t = {t:.3e} s"
 
 
+def pin_adaptive_scan(orc):
+    """Sec. 2.4 on uniformly moving sources: eta_min is the smallest
+    closed-form retarded distance, v_max the largest |v_target - v_source|
+    (the retarded velocity of a uniform source is its velocity), with and
+    without the eta_allow cutoff; the step rule and its clamps."""
+    T, w, v, x, w_now, vel = _uniform_case(seed=13)
+    rng = np.random.default_rng(14)
+    vt = 0.5 * C * rng.uniform(-1, 1, x.shape) / math.sqrt(3)
+    s = np.array([[uniform_light_distance(x[:, a] - w_now[:, j], vel[:, j] / C) for j in range(vel.shape[1])]
+                  for a in range(x.shape[1])])
+    sp = np.array([[np.linalg.norm(vt[:, a] - vel[:, j]) for j in range(vel.shape[1])] for a in range(x.shape[1])])
+    worst = 0.0
+    for allow in (0.0, float(np.median(s))):
+        keep = s >= allow
+        em, vm = orc.adaptive_scan(T, w, v, T[-1], x, None, vt, allow)
+        worst = max(worst, abs(em / s[keep].min() - 1), abs(vm / sp[keep].max() - 1))
+    want = 0.05 * s.min() / sp.max()
+    got = orc.adaptive_dt(s.min(), sp.max(), 0.05, 1e-30, 1.0)
+    clamps = (orc.adaptive_dt(1.0, 1.0, 0.05, 1e-15, 1e-12) == 1e-12
+              and orc.adaptive_dt(1e-9, 1e6, 0.05, 1e-15, 1e-12) == 1e-15
+              and orc.adaptive_dt(1e-3, 0.0, 0.05, 1e-15, 1e-12) == 1e-12)
+    ok = worst < 1e-12 and abs(got / want - 1) < 1e-15 and clamps
+    return ok, f"eta_min / v_max rel err {worst:.1e}; dt rule rel err {abs(got / want - 1):.1e}; clamps {clamps}"
+
+
+def pin_adaptive_step(orc):
+    """The adaptive stepper: when the rule saturates at dt_max it takes the
+    fixed-step trajectory (to rounding of the slot times); with a live rule
+    every stored segment still satisfies w_{k+1} = w_k + v_k (T_{k+1} - T_k)
+    and each step equals the rule applied to the state it starts from."""
+    spec = bunch.BunchSpec(12, (1e-3, 1e-3, 1e-3), 1.0, angle_spread=1.0, seed=15)
+    r, u = bunch.gaussian_bunch(spec)
+    D, dt = 16, 1e-13
+    T0, w0, v0 = orc.init_straight(r, u, D, dt)
+    run = oracle.OracleRun(orc, r, u, D=D, dt=dt, q=-QE, mass=ME)
+    run.step(6)
+    Ta, wa, va, ua, dts = orc.step_adaptive(T0, w0, v0, u, 6, q=-QE, mass=ME, c_dt=1e9, dt_min=1e-15, dt_max=dt)
+    sat = float(np.max(np.abs(wa[-1] - run.y))) / 1e-3
+    Tb, wb, vb, ub, db = orc.step_adaptive(T0, w0, v0, u, 6, q=-QE, mass=ME, c_dt=0.05, dt_min=1e-16,
+                                           dt_max=1e-12)
+    seg = float(np.max(np.abs(wb[1:] - (wb[:-1] + vb[:-1] * np.diff(Tb)[:, None, None]))))
+    Tc, wc, vc, uc, dc = orc.step_adaptive(Tb, wb, vb, ub, 1, q=-QE, mass=ME, c_dt=0.05, dt_min=1e-16,
+                                           dt_max=1e-12)
+    em, vm = orc.adaptive_scan(Tb, wb, vb, Tb[-1], wb[-1], np.arange(12), vb[-1], 0.0)
+    rule = orc.adaptive_dt(em, vm, 0.05, 1e-16, 1e-12)
+    live = bool(np.all(db < 1e-12) and np.all(db > 1e-16))
+    ok = sat < 1e-12 and np.all(dts == dt) and seg < 1e-18 and dc[0] == rule and live
+    return ok, (f"saturated vs fixed step {sat:.1e} of sigma; live steps {db[:3]} s; segment invariant {seg:.1e} m; "
+                f"next step {dc[0]:.4e} = rule {rule:.4e}")
+
+
 ALL_PINS = [
     pin_constants, pin_uniform_retarded_time, pin_heaviside_feynman, pin_heaviside_feynman_far, pin_coulomb, pin_before_history_field,
     pin_bracket_bruteforce, pin_tie_goes_older, pin_circle_reconstruction_order, pin_circle_field_convergence,
     pin_larmor, pin_hc_gyration, pin_hc_exb_drift, pin_dipole, pin_step_history, pin_diag,
-    pin_transport_free_and_dt_rule, pin_transport_mirror,
+    pin_transport_free_and_dt_rule, pin_transport_mirror, pin_adaptive_scan, pin_adaptive_step,
 ]

@@ -2,7 +2,8 @@
 MUT_* switches in oracle/empp_oracle.c) and check that the pins catch it.
 This shows that the pins constrain every step of the oracle: the
 bracket rule, the root, the reconstruction, the LW formula, B, the pusher,
-the dipole, the history update and the Stage-II transport."""
+the dipole, the history update, the adaptive step and the Stage-II
+transport."""
 import pytest
 
 import oracle
@@ -23,6 +24,8 @@ MUTANTS = [
     "MUT_ETA_ABSOLUTE",       # eta from the rounded absolute retarded position
     "MUT_TRANSPORT_DT_NO_GAMMA",  # Stage-II step from 1/|B| without gamma
     "MUT_TRANSPORT_OLD_V",    # Stage-II drift with the velocity before the kick
+    "MUT_ADAPT_NO_ALLOW",     # adaptive step ignores the eta_allow cutoff
+    "MUT_ADAPT_ETA_PRESENT",  # adaptive step from the present, not retarded, distance
 ]
 
 
