@@ -104,6 +104,16 @@ typedef struct {
     void *stream;          /* hipStream_t or NULL                            */
     void *workspace;       /* caller-owned device memory, or NULL            */
     uint64_t workspace_bytes;
+    /* Adaptive step (Sec. 2.4; FP64 path, guess modes other than MLP):
+     * each step is c_dt * eta_min / v_max clamped to [dt_min, dt_max], where
+     * eta_min = min |eta_ij| and v_max = max |v_i(t) - v_j(t_r)| over the
+     * pairs with |eta_ij| >= eta_allow, reduced in the same pair pass that
+     * sums the fields; dt then only spaces the straight-line prior history.
+     * adaptive = 0: fixed dt (the remaining fields are ignored).          */
+    int32_t adaptive;
+    double c_dt;           /* safety factor (the paper: 0.05)                */
+    double dt_min, dt_max; /* clamp (the paper: 1e-15 s and 1e-12 s)         */
+    double eta_allow;      /* pairs closer than this are left out (m, >= 0)  */
 } empp_config;
 
 typedef struct {
@@ -113,6 +123,7 @@ typedef struct {
     double mean_kinetic;   /* mean kinetic energy (gamma-1) m c^2, J (Sec. 2.7) */
     double t;              /* present time                                   */
     int64_t step;          /* steps taken since the history was set          */
+    double dt_last;        /* the last step's dt (adaptive), else cfg.dt     */
 } empp_diag;
 
 typedef struct {

@@ -47,13 +47,15 @@ class Config(ctypes.Structure):
         ("dipole_b0", ctypes.c_double), ("dipole_re", ctypes.c_double),
         ("precision", ctypes.c_int32), ("guess", ctypes.c_int32), ("device", ctypes.c_int32),
         ("source_splits", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
-        ("workspace_bytes", ctypes.c_uint64),
+        ("workspace_bytes", ctypes.c_uint64), ("adaptive", ctypes.c_int32), ("c_dt", ctypes.c_double),
+        ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double), ("eta_allow", ctypes.c_double),
     ]
 
 
 class Diag(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double * 3), ("sigma_xy", ctypes.c_double), ("centroid", ctypes.c_double * 3),
-                ("mean_kinetic", ctypes.c_double), ("t", ctypes.c_double), ("step", ctypes.c_int64)]
+                ("mean_kinetic", ctypes.c_double), ("t", ctypes.c_double), ("step", ctypes.c_int64),
+                ("dt_last", ctypes.c_double)]
 
 
 class Counters(ctypes.Structure):
@@ -232,7 +234,7 @@ def empp_get_diag(h):
     d = Diag()
     _check(lib.empp_get_diag(h, ctypes.byref(d)))
     return {"sigma": list(d.sigma), "sigma_xy": d.sigma_xy, "centroid": list(d.centroid),
-            "mean_kinetic": d.mean_kinetic, "t": d.t, "step": d.step}
+            "mean_kinetic": d.mean_kinetic, "t": d.t, "step": d.step, "dt_last": d.dt_last}
 
 
 def empp_set_counting(h, enable=True):
@@ -344,11 +346,14 @@ class Context:
     stream of ``device``."""
 
     def __init__(self, *, n, depth, q, m, dt, ext_field=0, dipole_b0=0.0, dipole_re=0.0,
-                 precision=EMPP_FP64, guess=EMPP_GUESS_BISECT, device=0, source_splits=0, use_torch=True):
+                 precision=EMPP_FP64, guess=EMPP_GUESS_BISECT, device=0, source_splits=0, use_torch=True,
+                 adaptive=False, c_dt=0.05, dt_min=1e-15, dt_max=1e-12, eta_allow=0.0):
         self.n, self.depth = int(n), int(depth)
         cfg = Config(n=self.n, depth=self.depth, ext_field=int(ext_field), q=float(q), m=float(m), dt=float(dt),
                      dipole_b0=float(dipole_b0), dipole_re=float(dipole_re), precision=int(precision),
-                     guess=int(guess), device=int(device), source_splits=int(source_splits))
+                     guess=int(guess), device=int(device), source_splits=int(source_splits),
+                     adaptive=int(bool(adaptive)), c_dt=float(c_dt), dt_min=float(dt_min), dt_max=float(dt_max),
+                     eta_allow=float(eta_allow))
         self._ws = None
         self.stream_handle = None
         if use_torch:

@@ -84,7 +84,7 @@ constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, order, pos, skey, st, kc, kc_bytes, total;
+    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, order, pos, skey, st, ad, kc, kc_bytes, total;
 };
 
 int tile_for_depth(int D) { return pair_fp64_tile(D); }
@@ -175,6 +175,8 @@ Layout layout_for(const empp_config &c)
     L.pos = take(N * sizeof(double4));
     L.skey = take(4 * sizeof(unsigned long long));
     L.st = take(sizeof(double));
+    // adaptive step: two {eta_min, v_max^2} slots and the last dt
+    L.ad = take(8 * sizeof(unsigned long long));
     // previous-step brackets (warm start): uint16 per (source, target)
     L.kc_bytes = c.guess == EMPP_GUESS_PREVIOUS ? N * N * sizeof(uint16_t) : 0;
     L.kc = L.kc_bytes ? take(L.kc_bytes) : 0;
@@ -208,6 +210,13 @@ empp_status validate(const empp_config *c)
         return fail(EMPP_EINVAL, "unknown guess mode %d", c->guess);
     if (c->guess == EMPP_GUESS_PREVIOUS && c->precision == EMPP_MIXED)
         return fail(EMPP_EUNSUPPORTED, "warm-start brackets are implemented for the FP64 path");
+    if (c->adaptive) {
+        if (c->precision != EMPP_FP64 || c->guess == EMPP_GUESS_MLP || c->guess == EMPP_GUESS_MLP_PAIR)
+            return fail(EMPP_EUNSUPPORTED, "the adaptive step is implemented for the FP64 path without the surrogate");
+        if (!(c->c_dt > 0.0) || !(c->dt_min > 0.0) || !(c->dt_max >= c->dt_min) || !std::isfinite(c->dt_max) ||
+            !(c->eta_allow >= 0.0))
+            return fail(EMPP_EINVAL, "adaptive step needs c_dt > 0, 0 < dt_min <= dt_max finite, eta_allow >= 0");
+    }
     return EMPP_OK;
 }
 
@@ -275,6 +284,7 @@ struct empp_ctx {
     double4 *pos() const { return at<double4>(L.pos); }
     unsigned long long *skey() const { return at<unsigned long long>(L.skey); }
     double *stime() const { return at<double>(L.st); }
+    unsigned long long *ad() const { return at<unsigned long long>(L.ad); }
     // present positions: the ring's newest slot (Stage I) or the compact
     // array viewed as a one-slot ring (Stage II)
     const double4 *present_pos() const { return handed_off ? pos() : ring_w(); }
@@ -314,6 +324,17 @@ empp_status check_err(empp_ctx *ctx)
     return EMPP_OK;
 }
 
+// Both {eta_min, v_max^2} slots empty, last dt = cfg.dt.
+empp_status reset_adaptive(empp_ctx *ctx)
+{
+    double dt = ctx->cfg.dt;
+    unsigned long long init[8] = {kPosInfBits, 0ull, kPosInfBits, 0ull, 0ull, 0ull, 0ull, 0ull};
+    memcpy(&init[4], &dt, sizeof dt);
+    HIP_TRY(hipMemcpyAsync(ctx->ad(), init, sizeof init, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return EMPP_OK;
+}
+
 PairParams pair_params(empp_ctx *ctx)
 {
     PairParams p{};
@@ -341,6 +362,8 @@ PairParams pair_params(empp_ctx *ctx)
         p.guess = EMPP_GUESS_BISECT;
     p.kc = nullptr;
     p.kc_cold = 1;
+    p.ad = nullptr;
+    p.eta_allow = ctx->cfg.eta_allow;
     p.dt = ctx->cfg.dt;
     return p;
 }
@@ -579,6 +602,8 @@ empp_status empp_init_history_straight(empp_ctx *ctx)
     ctx->have_history = true;
     ctx->handed_off = false;
     ctx->kc_valid = false;
+    if ((st = reset_adaptive(ctx)) != EMPP_OK)
+        return st;
     ctx->handed_off = false;
     return EMPP_OK;
 }
@@ -639,6 +664,8 @@ empp_status empp_set_history(empp_ctx *ctx, int32_t nslots, const double *T, con
     ctx->have_history = true;
     ctx->handed_off = false;
     ctx->kc_valid = false;
+    if ((st = reset_adaptive(ctx)) != EMPP_OK)
+        return st;
     ctx->handed_off = false;
     return EMPP_OK;
 }
@@ -675,6 +702,10 @@ empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
             p.kc = ctx->kc();
             p.kc_cold = ctx->kc_valid ? 0 : 1;
         }
+        unsigned long long *slot = ctx->ad() + 2 * (ctx->step & 1);
+        unsigned long long *other = ctx->ad() + 2 * ((ctx->step + 1) & 1);
+        if (ctx->cfg.adaptive)
+            p.ad = slot;
         HIP_TRY(launch_pair(ctx, p, false));
         ctx->kc_valid = p.kc != nullptr;
         PushParams q{};
@@ -696,10 +727,27 @@ empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
         q.ext_field = ctx->cfg.ext_field;
         q.dip_k = ctx->cfg.dipole_b0 * ctx->cfg.dipole_re * ctx->cfg.dipole_re * ctx->cfg.dipole_re;
         q.self_field = 1;
+        if (ctx->cfg.adaptive) {
+            q.ad = slot;
+            q.ad_next = other;
+            q.dt_out = reinterpret_cast<double *>(ctx->ad() + 4);
+            q.c_dt = ctx->cfg.c_dt;
+            q.dt_min = ctx->cfg.dt_min;
+            q.dt_max = ctx->cfg.dt_max;
+            q.q = ctx->cfg.q;
+            q.m = ctx->cfg.m;
+        }
         HIP_TRY(timed(ctx, 1, [&]() { return launch_push(q, ctx->stream); }));
         ctx->head = ctx->head + 1 == ctx->cfg.depth ? 0 : ctx->head + 1;
         ctx->step += 1;
         ctx->t_now = q.t_next;
+    }
+    if (ctx->cfg.adaptive && nsteps > 0) {
+        // the steps were chosen on the device: bring the clock back
+        double tn = 0.0;
+        HIP_TRY(hipMemcpyAsync(&tn, ctx->T() + ctx->head, sizeof tn, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        ctx->t_now = tn;
     }
     return EMPP_OK;
 }
@@ -980,6 +1028,11 @@ empp_status empp_get_diag(empp_ctx *ctx, empp_diag *out)
     out->mean_kinetic = s[6] * inv * ctx->cfg.m * kC_LIGHT * kC_LIGHT;
     out->t = ctx->t_now;
     out->step = ctx->step;
+    out->dt_last = ctx->cfg.dt;
+    if (ctx->cfg.adaptive) {
+        HIP_TRY(hipMemcpyAsync(&out->dt_last, ctx->ad() + 4, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
     return EMPP_OK;
 }
 
@@ -1569,6 +1622,8 @@ empp_status empp_load(empp_ctx *ctx, const char *path)
     ctx->have_history = true;
     ctx->handed_off = h.stage == 2;
     ctx->kc_valid = false;
+    if ((st = reset_adaptive(ctx)) != EMPP_OK)
+        return st;
     ctx->head = h.head;
     ctx->step = h.step;
     ctx->tr_step = h.tr_step;

@@ -33,7 +33,7 @@ struct PairParams {
     int64_t n_src;      // sources N
     int32_t D;
     int32_t head;       // physical index of the newest slot
-    double t;           // present time (== T[head])
+    double t;           // present time (== T[head]; the pair kernels read T[head])
     double kq;          // Coulomb constant times source charge
     // targets: external points x[3][m] (x != nullptr) or the particles'
     // newest positions (x == nullptr, then target a is particle a and the
@@ -65,6 +65,11 @@ struct PairParams {
     // written by it; on a cold step the bisection fills it.
     uint16_t *kc;
     int32_t kc_cold;
+    // adaptive step (Sec. 2.4): min |eta| and max |v_i - v_j(t_r)|^2 over
+    // the pairs with |eta| >= eta_allow, folded into ad[0] (atomicMin) and
+    // ad[1] (atomicMax) as double bit patterns; null when the step is fixed
+    unsigned long long *ad;
+    double eta_allow;
 };
 
 constexpr uint16_t kBracketBefore = 0xFFFF;
@@ -88,6 +93,14 @@ struct PushParams {
     int32_t ext_field;
     double dip_k;       // b0 * re^3: (mu0/4pi) M0 for the centred dipole
     int32_t self_field; // 0: stage-II transport (E = 0, B = B_geo only)
+    // adaptive step: ad = this step's {eta_min, v_max^2} slot (null: fixed
+    // dt); the step is c_dt eta_min / v_max clamped to [dt_min, dt_max],
+    // t_now is read from T[head], and ad_next/dt_out are reset/written
+    unsigned long long *ad;
+    unsigned long long *ad_next;
+    double *dt_out;
+    double c_dt, dt_min, dt_max;
+    double q, m;
 };
 
 // Block of a pair-kernel launch -> (target block bx, source chunk split).

@@ -42,7 +42,7 @@ __device__ inline double sqrt_pos(double x)
 // velocity records of the bracket ends.  Writes E and B into f[0..5].
 // Returns false on a numerical failure (negative discriminant, eta <= 0).
 __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, double L1, double4 v1, double4 v2,
-                               bool before, double kq, double f[6])
+                               bool before, double kq, double f[6], double &eta_len, double3 &v_ret)
 {
     const double c = kC_LIGHT;
     const double c2 = c * c;
@@ -87,12 +87,14 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
     f[3] = (hy * Ez - hz * Ey) * ic;
     f[4] = (hz * Ex - hx * Ez) * ic;
     f[5] = (hx * Ey - hy * Ex) * ic;
+    eta_len = en;
+    v_ret = make_double3(vrx, vry, vrz);
     return ok;
 }
 
 }  // namespace
 
-template <bool KSTAR, bool COUNT, int GUESS, int S>
+template <bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT>
 __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
 {
     extern __shared__ double4 lds[];
@@ -111,6 +113,8 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
         j1 = p.n_src;
 
     double rx = 0, ry = 0, rz = 0;
+    double3 vt = make_double3(0.0, 0.0, 0.0);  // target's present velocity (adaptive step)
+    double eta_min = __longlong_as_double((long long)kPosInfBits), dv2_max = 0.0;
     int64_t self = -1, tgt = a;  // tgt: index the outputs are written at
     if (active) {
         if (p.x) {
@@ -125,6 +129,10 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
             ry = w.y;
             rz = w.z;
             self = tgt;
+            if (ADAPT) {
+                double4 vn = p.ring_v[tgt * D + p.head];
+                vt = make_double3(vn.x, vn.y, vn.z);
+            }
         }
     }
     double sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
@@ -139,10 +147,12 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
     // every logical slot (shared by all sources).
     const int nbuf = p.nbuf;
     double *Ls = reinterpret_cast<double *>(lds + nbuf * S * D);
+    // the present time is the newest slot's (the clock lives in T)
+    const double tnow = p.T[p.head];
     for (int b = tid; b < D; b += kBlock) {
         int ph = p.head - b;
         ph += ph < 0 ? D : 0;
-        Ls[b] = kC_LIGHT * (p.t - p.T[ph]);
+        Ls[b] = kC_LIGHT * (tnow - p.T[ph]);
     }
     // Tile records are prefetched into registers one tile ahead (the first
     // two records of each thread), so their HBM/L2 latency overlaps the
@@ -271,13 +281,19 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
             auto finish = [&](int s, int b, double4 v1, double4 v2) {
                 const bool before = b < 0;
                 const int bb = before ? D - 1 : b;
-                double f[6];
-                bool ok = lw_pair(rx, ry, rz, cur[s * D + bb], Ls[bb], v1, v2, before, p.kq, f);
+                double f[6], en;
+                double3 vr;
+                bool ok = lw_pair(rx, ry, rz, cur[s * D + bb], Ls[bb], v1, v2, before, p.kq, f, en, vr);
                 if (valid[s]) {
                     if (ok) {
 #pragma unroll
                         for (int k = 0; k < 6; ++k)
                             acc[k] += f[k];
+                        if (ADAPT && en >= p.eta_allow) {
+                            const double dx = vt.x - vr.x, dy = vt.y - vr.y, dz = vt.z - vr.z;
+                            eta_min = fmin(eta_min, en);
+                            dv2_max = fmax(dv2_max, dx * dx + dy * dy + dz * dz);
+                        }
                     } else {
                         if (!failed)
                             fail_j = (int32_t)jj[s];
@@ -445,6 +461,17 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
         if (failed)
             report_error(p.err, tgt, fail_j, kErrCoincident);
     }
+    if (ADAPT) {
+        // one atomic pair per wavefront
+        for (int off = 32; off > 0; off >>= 1) {
+            eta_min = fmin(eta_min, __shfl_xor(eta_min, off));
+            dv2_max = fmax(dv2_max, __shfl_xor(dv2_max, off));
+        }
+        if ((tid & 63) == 0) {
+            atomicMin(&p.ad[0], (unsigned long long)__double_as_longlong(eta_min));
+            atomicMax(&p.ad[1], (unsigned long long)__double_as_longlong(dv2_max));
+        }
+    }
     if (COUNT) {
         // one atomic per wavefront
         unsigned long long c0 = npairs, c1 = nbefore, c2 = probes, c3 = nfall;
@@ -481,43 +508,53 @@ int pair_fp64_nbuf(int D, int tile)
 hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar, bool count)
 {
     PairParams p = p0;
+    if (p.ad)
+        p.tile = 1;  // the adaptive reductions need the registers of a second tile source
     p.nbuf = pair_fp64_nbuf(p.D, p.tile);
     const int64_t nblocks = (p.m + kBlock - 1) / kBlock * p.nsplit;
     if (nblocks < 1 || nblocks > INT32_MAX)
         return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nblocks);
     size_t lds = (size_t)p.nbuf * p.tile * p.D * sizeof(double4) + (size_t)p.D * sizeof(double);
-#define EMPP_LAUNCH(K, C, G, S)                                                                              \
+#define EMPP_LAUNCH(K, C, G, S, A)                                                                           \
     do {                                                                                                    \
         if (lds > 65536)                                                                                    \
-            (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, C, G, S>,                           \
+            (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, C, G, S, A>,                        \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-        hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S>), grid, dim3(kBlock), lds, stream, p);             \
+        hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S, A>), grid, dim3(kBlock), lds, stream, p);          \
     } while (0)
-#define EMPP_BY_TILE(K, C, G) \
-    do { if (p.tile == 2) EMPP_LAUNCH(K, C, G, 2); else EMPP_LAUNCH(K, C, G, 1); } while (0)
-#define EMPP_BY_GUESS(K, C)                                                                                  \
-    do {                                                                                                    \
-        if (p.guess == 2) EMPP_BY_TILE(K, C, 2);                                                             \
-        else if (p.guess == 1) EMPP_BY_TILE(K, C, 1);                                                        \
-        else EMPP_BY_TILE(K, C, 0);                                                                          \
-    } while (0)
+#define EMPP_BY_TILE(K, C, G, A) \
+    do { if (p.tile == 2) EMPP_LAUNCH(K, C, G, 2, A); else EMPP_LAUNCH(K, C, G, 1, A); } while (0)
+#define EMPP_BY_ADAPT(C, G) \
+    do { if (p.ad) EMPP_LAUNCH(false, C, G, 1, true); else EMPP_BY_TILE(false, C, G, false); } while (0)
+    if (p.ad && (kstar || p.x || p.guess == 1))
+        return hipErrorInvalidValue;  // the adaptive step is taken in step mode
     if (p.guess == 4) {
         // warm start: step mode only (no per-pair k* output); the first
         // step of a run bisects and fills the cache (search mode 5)
         if (kstar || !p.kc || p.x)
             return hipErrorInvalidValue;
         if (p.kc_cold) {
-            if (count) EMPP_BY_TILE(false, true, 5); else EMPP_BY_TILE(false, false, 5);
+            if (count) EMPP_BY_ADAPT(true, 5); else EMPP_BY_ADAPT(false, 5);
         } else {
-            if (count) EMPP_BY_TILE(false, true, 4); else EMPP_BY_TILE(false, false, 4);
+            if (count) EMPP_BY_ADAPT(true, 4); else EMPP_BY_ADAPT(false, 4);
         }
     } else if (kstar) {
-        if (count) EMPP_BY_GUESS(true, true); else EMPP_BY_GUESS(true, false);
+        if (p.guess == 2) {
+            if (count) EMPP_BY_TILE(true, true, 2, false); else EMPP_BY_TILE(true, false, 2, false);
+        } else if (p.guess == 1) {
+            if (count) EMPP_BY_TILE(true, true, 1, false); else EMPP_BY_TILE(true, false, 1, false);
+        } else {
+            if (count) EMPP_BY_TILE(true, true, 0, false); else EMPP_BY_TILE(true, false, 0, false);
+        }
+    } else if (p.guess == 1) {
+        if (count) EMPP_BY_TILE(false, true, 1, false); else EMPP_BY_TILE(false, false, 1, false);
+    } else if (p.guess == 2) {
+        if (count) EMPP_BY_ADAPT(true, 2); else EMPP_BY_ADAPT(false, 2);
     } else {
-        if (count) EMPP_BY_GUESS(false, true); else EMPP_BY_GUESS(false, false);
+        if (count) EMPP_BY_ADAPT(true, 0); else EMPP_BY_ADAPT(false, 0);
     }
-#undef EMPP_BY_GUESS
+#undef EMPP_BY_ADAPT
 #undef EMPP_BY_TILE
 #undef EMPP_LAUNCH
     return hipGetLastError();

@@ -156,10 +156,12 @@ __global__ __launch_bounds__(kBlock) void pair_mixed_kernel(PairParams p)
             self = tgt;
         }
     }
+    // the present time is the newest slot's (the clock lives in T)
+    const double tnow = p.T[p.head];
     for (int b = tid; b < D; b += kBlock) {
         int ph = p.head - b;
         ph += ph < 0 ? D : 0;
-        Ls[b] = kC_LIGHT * (p.t - p.T[ph]);
+        Ls[b] = kC_LIGHT * (tnow - p.T[ph]);
     }
     __syncthreads();
     const double Lmax = Ls[D - 1];

@@ -79,6 +79,24 @@ __device__ inline void higuera_cary(double &ux, double &uy, double &uz, double E
 __global__ void push_kernel(PushParams p)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p.ad) {
+        // Sec. 2.4: this step's dt from the pair kernel's reductions (the
+        // same value in every thread); the clock lives in T[head]
+        const double eta_min = __longlong_as_double((long long)p.ad[0]);
+        const double v_max = sqrt(__longlong_as_double((long long)p.ad[1]));
+        double dt = p.dt_max;
+        if (v_max > 0.0 && eta_min < __longlong_as_double((long long)kPosInfBits))
+            dt = fmin(p.dt_max, fmax(p.dt_min, p.c_dt * eta_min / v_max));
+        p.dt = dt;
+        p.eps = p.q * dt / (2.0 * p.m);
+        p.t_now = p.T[p.head];
+        p.t_next = p.t_now + dt;
+        if (i == 0) {
+            p.ad_next[0] = kPosInfBits;
+            p.ad_next[1] = 0ull;
+            p.dt_out[0] = dt;
+        }
+    }
     if (i >= p.N)
         return;
     const int D = p.D;
