@@ -114,6 +114,10 @@ typedef struct {
     double c_dt;           /* safety factor (the paper: 0.05)                */
     double dt_min, dt_max; /* clamp (the paper: 1e-15 s and 1e-12 s)         */
     double eta_allow;      /* pairs closer than this are left out (m, >= 0)  */
+    /* Reconstruction inside the bracket: 0 = the local linear one of
+     * Sec. 2.2 (Eq. linear, the method); 1 = the earlier midpoint values of
+     * Eq. (mid), an accuracy ablation (FP64 path, bisection, fixed step).  */
+    int32_t recon;
 } empp_config;
 
 typedef struct {

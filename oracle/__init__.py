@@ -83,6 +83,8 @@ class Oracle:
                                   ctypes.c_int, _P]
         L.oracle_diag.argtypes = [_I64, _P, _P, _D, _P]
         L.oracle_diag.restype = None
+        L.oracle_set_reconstruction.argtypes = [ctypes.c_int]
+        L.oracle_set_reconstruction.restype = None
         L.oracle_transport.argtypes = [_I64, _D, _D, _I32, _D, _D, _D, _D, _P, _P, _P, _I64, _P]
         L.oracle_transport.restype = ctypes.c_int
         L.oracle_adaptive_scan.argtypes = [_I64, _I32, _P, _P, _P, _D, _I64, _P, _P, _P, _D, _P]
@@ -164,6 +166,11 @@ class Oracle:
         if st != OR_OK:
             raise OracleError(st)
         return T, w, v
+
+    def set_reconstruction(self, mode):
+        """0: the local linear reconstruction (Eq. linear); 1: the midpoint
+        values of Eq. (mid), for the accuracy ablation."""
+        self.L.oracle_set_reconstruction(int(mode))
 
     def transport(self, y, u, t, *, q, mass, dt_max, frac, nsteps, ext_field=0, b0=0.0, re=0.0):
         """Stage II (E = 0, B = B_geo): returns (y, u, t, last dt)."""

@@ -118,6 +118,13 @@ static void load_sample(const double *a, int64_t N, int32_t s, int64_t j, double
     out[2] = a[((int64_t)s * 3 + 2) * N + j];
 }
 
+/* Reconstruction inside the bracket: 0 = the local linear one of Sec. 2.2
+ * (Eq. linear, the method), 1 = the earlier midpoint values (Eq. mid),
+ * kept as an accuracy ablation.  Set before a call, read-only during it. */
+static int g_recon = 0;
+
+void oracle_set_reconstruction(int mode) { g_recon = mode == 1 ? 1 : 0; }
+
 /* Retarded quantities of one (target, source) pair.                         */
 typedef struct {
     int32_t slot;     /* left end of the bracket (logical slot, 0 = oldest) */
@@ -233,6 +240,22 @@ static int solve_retarded(int64_t N, int32_t ns, const double *T, const double *
 #else
             out->ar[c] = 0.0;
 #endif
+        }
+    } else if (g_recon == 1) {
+        /* Eq. (mid): t_r, w, v at the bracket's midpoint, a from the
+         * velocity difference; eta = r - (w_1 + w_2)/2 formed relative to
+         * w_1 as above.                                                    */
+        double w2[3], v2[3];
+        load_sample(w, N, s1 + 1, j, w2);
+        load_sample(v, N, s1 + 1, j, v2);
+        double h = T[s1 + 1] - T[s1];
+        out->dt_root = 0.5 * h;
+        out->tr = 0.5 * (T[s1] + T[s1 + 1]);
+        for (int c = 0; c < 3; ++c) {
+            out->wr[c] = 0.5 * (w1[c] + w2[c]);
+            out->eta[c] = d[c] - 0.5 * (w2[c] - w1[c]);
+            out->vr[c] = 0.5 * (v1[c] + v2[c]);
+            out->ar[c] = (v2[c] - v1[c]) / h;
         }
     } else {
         double v2[3];

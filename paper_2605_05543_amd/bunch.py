@@ -83,6 +83,24 @@ def paper_beam(n, *, e0_mev=1.0, delta_e=0.01, emittance=1e-6, r_perp=2e-3, r_pa
     return r, vel * g
 
 
+def beam_rotation(theta, phi):
+    """R(theta, phi) = R_z(phi) R_y(theta) of Sec. 2.5: takes the beam axis
+    (+z of the beam frame) to polar angle theta and azimuth phi in the
+    laboratory frame."""
+    ct, st, cp, sp = math.cos(theta), math.sin(theta), math.cos(phi), math.sin(phi)
+    Ry = np.array([[ct, 0.0, st], [0.0, 1.0, 0.0], [-st, 0.0, ct]])
+    Rz = np.array([[cp, -sp, 0.0], [sp, cp, 0.0], [0.0, 0.0, 1.0]])
+    return Rz @ Ry
+
+
+def rotate_to_lab(r, u, theta, phi, center=(0.0, 0.0, 0.0)):
+    """Beam-frame positions and proper velocities [3, N] -> laboratory frame
+    (Sec. 2.5: x_lab = R x_beam, v_lab = R v_beam; u = gamma v rotates the
+    same way), the rotated bunch then centred on ``center``."""
+    R = beam_rotation(theta, phi)
+    return R @ np.asarray(r) + np.asarray(center, dtype=np.float64).reshape(3, 1), R @ np.asarray(u)
+
+
 @dataclasses.dataclass(frozen=True)
 class Workload:
     """One synthetic workload: bunch, history depth, step, steps, field."""

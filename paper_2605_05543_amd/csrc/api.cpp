@@ -210,6 +210,10 @@ empp_status validate(const empp_config *c)
         return fail(EMPP_EINVAL, "unknown guess mode %d", c->guess);
     if (c->guess == EMPP_GUESS_PREVIOUS && c->precision == EMPP_MIXED)
         return fail(EMPP_EUNSUPPORTED, "warm-start brackets are implemented for the FP64 path");
+    if (c->recon != 0 && c->recon != 1)
+        return fail(EMPP_EINVAL, "recon must be 0 (linear) or 1 (midpoint)");
+    if (c->recon == 1 && (c->precision != EMPP_FP64 || c->guess != EMPP_GUESS_BISECT || c->adaptive))
+        return fail(EMPP_EUNSUPPORTED, "the midpoint ablation runs on the FP64 path with bisection and a fixed step");
     if (c->adaptive) {
         if (c->precision != EMPP_FP64 || c->guess == EMPP_GUESS_MLP || c->guess == EMPP_GUESS_MLP_PAIR)
             return fail(EMPP_EUNSUPPORTED, "the adaptive step is implemented for the FP64 path without the surrogate");
@@ -364,6 +368,7 @@ PairParams pair_params(empp_ctx *ctx)
     p.kc_cold = 1;
     p.ad = nullptr;
     p.eta_allow = ctx->cfg.eta_allow;
+    p.recon = ctx->cfg.recon;
     p.dt = ctx->cfg.dt;
     return p;
 }

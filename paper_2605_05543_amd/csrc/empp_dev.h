@@ -70,6 +70,9 @@ struct PairParams {
     // ad[1] (atomicMax) as double bit patterns; null when the step is fixed
     unsigned long long *ad;
     double eta_allow;
+    // reconstruction inside the bracket: 0 = local linear (Eq. linear, the
+    // method), 1 = midpoint values (Eq. mid, accuracy ablation)
+    int32_t recon;
 };
 
 constexpr uint16_t kBracketBefore = 0xFFFF;

@@ -42,7 +42,8 @@ __device__ inline double sqrt_pos(double x)
 // velocity records of the bracket ends.  Writes E and B into f[0..5].
 // Returns false on a numerical failure (negative discriminant, eta <= 0).
 __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, double L1, double4 v1, double4 v2,
-                               bool before, double kq, double f[6], double &eta_len, double3 &v_ret)
+                               bool before, double kq, double f[6], double &eta_len, double3 &v_ret, bool mid,
+                               double4 w2)
 {
     const double c = kC_LIGHT;
     const double c2 = c * c;
@@ -65,6 +66,17 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
     double ex = dx - v1.x * dtr, ey = dy - v1.y * dtr, ez = dz - v1.z * dtr;  // eta
     // |eta| = c (t - t_r) on the reconstructed segment
     double en = L1 - c * dtr;
+    if (mid && !before) {
+        // Eq. (mid): the bracket ends' means, eta = r - (w_1 + w_2)/2
+        ex = dx - 0.5 * (w2.x - w1.x);
+        ey = dy - 0.5 * (w2.y - w1.y);
+        ez = dz - 0.5 * (w2.z - w1.z);
+        en = sqrt(ex * ex + ey * ey + ez * ez);
+        vrx = 0.5 * (v1.x + v2.x);
+        vry = 0.5 * (v1.y + v2.y);
+        vrz = 0.5 * (v1.z + v2.z);
+        ok = true;
+    }
     double ev = c * en - (ex * vrx + ey * vry + ez * vrz);  // eta . v'
     ok = ok && (en > 0.0) && (ev > 0.0);
     double inv = rcp64(en * ev);
@@ -94,7 +106,7 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
 
 }  // namespace
 
-template <bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT>
+template <bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID = false>
 __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
 {
     extern __shared__ double4 lds[];
@@ -283,7 +295,8 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                 const int bb = before ? D - 1 : b;
                 double f[6], en;
                 double3 vr;
-                bool ok = lw_pair(rx, ry, rz, cur[s * D + bb], Ls[bb], v1, v2, before, p.kq, f, en, vr);
+                bool ok = lw_pair(rx, ry, rz, cur[s * D + bb], Ls[bb], v1, v2, before, p.kq, f, en, vr, MID,
+                                  MID ? cur[s * D + (bb > 0 ? bb - 1 : 0)] : make_double4(0.0, 0.0, 0.0, 0.0));
                 if (valid[s]) {
                     if (ok) {
 #pragma unroll
@@ -508,8 +521,8 @@ int pair_fp64_nbuf(int D, int tile)
 hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar, bool count)
 {
     PairParams p = p0;
-    if (p.ad)
-        p.tile = 1;  // the adaptive reductions need the registers of a second tile source
+    if (p.ad || p.recon == 1)
+        p.tile = 1;  // the adaptive reductions and the midpoint ablation use one-source tiles
     p.nbuf = pair_fp64_nbuf(p.D, p.tile);
     const int64_t nblocks = (p.m + kBlock - 1) / kBlock * p.nsplit;
     if (nblocks < 1 || nblocks > INT32_MAX)
@@ -523,12 +536,29 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
         hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S, A>), grid, dim3(kBlock), lds, stream, p);          \
     } while (0)
+#define EMPP_LAUNCH_MID(K)                                                                                   \
+    do {                                                                                                    \
+        if (lds > 65536)                                                                                    \
+            (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, false, 0, 1, false, true>,          \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+        hipLaunchKernelGGL((pair_fp64_kernel<K, false, 0, 1, false, true>), grid, dim3(kBlock), lds, stream, p); \
+    } while (0)
 #define EMPP_BY_TILE(K, C, G, A) \
     do { if (p.tile == 2) EMPP_LAUNCH(K, C, G, 2, A); else EMPP_LAUNCH(K, C, G, 1, A); } while (0)
 #define EMPP_BY_ADAPT(C, G) \
     do { if (p.ad) EMPP_LAUNCH(false, C, G, 1, true); else EMPP_BY_TILE(false, C, G, false); } while (0)
     if (p.ad && (kstar || p.x || p.guess == 1))
         return hipErrorInvalidValue;  // the adaptive step is taken in step mode
+    if (p.recon == 1) {
+        // midpoint ablation: the paper's bisection, fixed step, any target mode
+        if (p.ad || count)
+            return hipErrorInvalidValue;
+        if (kstar)
+            EMPP_LAUNCH_MID(true);
+        else
+            EMPP_LAUNCH_MID(false);
+        return hipGetLastError();
+    }
     if (p.guess == 4) {
         // warm start: step mode only (no per-pair k* output); the first
         // step of a run bisects and fills the cache (search mode 5)
@@ -555,6 +585,7 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
         if (count) EMPP_BY_ADAPT(true, 0); else EMPP_BY_ADAPT(false, 0);
     }
 #undef EMPP_BY_ADAPT
+#undef EMPP_LAUNCH_MID
 #undef EMPP_BY_TILE
 #undef EMPP_LAUNCH
     return hipGetLastError();

@@ -368,6 +368,48 @@ def pin_circle_field_convergence(orc):
     return ok, f"rel field errors {errs}; ratios E {rE:.2f} B {rB:.2f}"
 
 
+def pin_midpoint_reconstruction(orc):
+    """Eq. (mid), the earlier reconstruction kept as an ablation: inside the
+    bracket found by the same search it returns exactly the bracket ends'
+    means (t, w, v) and their velocity difference over dt; on the circular
+    orbit its w(t_r) converges at first order only, and its field error is
+    larger than the linear reconstruction's at the same step."""
+    try:
+        orc.set_reconstruction(1)
+        T, w, v, x, rho, om = _circle_case(400, 3200)
+        out = orc.retarded(T, w, v, T[-1], x)
+        ns = len(T)
+        exact = True
+        for a in range(x.shape[1]):
+            b = int(out["kstar"][a, 0])
+            if b < 0:
+                continue
+            k = ns - 1 - b
+            exact &= bool(np.array_equal(out["wr"][a, 0], 0.5 * (w[k, :, 0] + w[k + 1, :, 0])))
+            exact &= bool(np.array_equal(out["vr"][a, 0], 0.5 * (v[k, :, 0] + v[k + 1, :, 0])))
+            exact &= bool(out["tr"][a, 0] == 0.5 * (T[k] + T[k + 1]))
+        errs = []
+        for spp in (400, 800):
+            T, w, v, x, rho, om = _circle_case(spp, int(8 * spp))
+            o = orc.retarded(T, w, v, T[-1], x)
+            we, _, _ = circle_orbit(circle_retarded_time(x, T[-1], rho, om), rho, om)
+            errs.append(np.max(np.linalg.norm(o["wr"][:, 0, :].T - we, axis=0)) / rho)
+        T, w, v, x, rho, om = _circle_case(400, 3200, seed=42)
+        tr = circle_retarded_time(x, T[-1], rho, om)
+        we, ve, ae = circle_orbit(tr, rho, om)
+        Ee, Be = lw_kappa_form(x, we, ve, ae, QE)
+        Em, _ = orc.fields(T, w, v, QE, T[-1], x)
+        orc.set_reconstruction(0)
+        El, _ = orc.fields(T, w, v, QE, T[-1], x)
+    finally:
+        orc.set_reconstruction(0)
+    em, el = _vec_rel(Em, Ee), _vec_rel(El, Ee)
+    ratio = errs[0] / errs[1]
+    ok = exact and 1.6 < ratio < 2.6 and em > el
+    return ok, (f"bracket means exact {exact}; w(t_r) error ratio {ratio:.2f} (first order); field error "
+                f"midpoint {em:.2e} vs linear {el:.2e}")
+
+
 def larmor_flux(orc, steps_per_period=800, rho=1e-3, beta=0.5, Rs_over=3.0, nth=48, nph=96):
     """Poynting flux of a charge on a circular orbit through a sphere of
     radius Rs centred on the orbit, and Lienard's power q^2 g^4 a^2 /
@@ -634,4 +676,5 @@ ALL_PINS = [
     pin_bracket_bruteforce, pin_tie_goes_older, pin_circle_reconstruction_order, pin_circle_field_convergence,
     pin_larmor, pin_hc_gyration, pin_hc_exb_drift, pin_dipole, pin_step_history, pin_diag,
     pin_transport_free_and_dt_rule, pin_transport_mirror, pin_adaptive_scan, pin_adaptive_step,
+    pin_midpoint_reconstruction,
 ]

@@ -67,3 +67,23 @@ def test_histories_move_at_stored_velocity():
     T, w, v = bunch.wiggly_history(3, 20, 1e-13, seed=1)
     assert np.max(np.abs(w[1:] - (w[:-1] + v[:-1] * np.diff(T)[:, None, None]))) < 1e-18
     assert np.all(np.linalg.norm(v, axis=1) < C)
+
+
+def test_beam_rotation():
+    """R(theta, phi) = R_z(phi) R_y(theta) (Sec. 2.5) is a proper rotation
+    taking the beam axis to (sin t cos p, sin t sin p, cos t); rotating a
+    sampled beam keeps speeds, distances and the centroid offset."""
+    th, ph = 0.7, -1.9
+    R = bunch.beam_rotation(th, ph)
+    assert np.allclose(R @ R.T, np.eye(3), atol=1e-15) and abs(np.linalg.det(R) - 1) < 1e-15
+    assert np.allclose(R @ [0, 0, 1], [np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], atol=1e-15)
+    assert np.allclose(bunch.beam_rotation(0.0, 0.0), np.eye(3))
+    r, u = bunch.paper_beam(200, seed=3)
+    center = (3 * bunch.R_EARTH, 0.0, 0.0)
+    rl, ul = bunch.rotate_to_lab(r, u, th, ph, center)
+    assert np.allclose(np.linalg.norm(ul, axis=0), np.linalg.norm(u, axis=0), rtol=1e-15)
+    d0 = np.linalg.norm(r[:, 3] - r[:, 17])
+    d1 = np.linalg.norm(rl[:, 3] - rl[:, 17])
+    assert abs(d1 / d0 - 1) < 2e-5  # coordinates of 3 R_E round to 3.7 nm
+    mean_dir = ul.mean(axis=1) / np.linalg.norm(ul.mean(axis=1))
+    assert mean_dir @ (R @ [0, 0, 1]) > 0.999

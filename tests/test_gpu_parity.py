@@ -207,3 +207,30 @@ def test_errors_are_reported(orc):
         # the same target with source 4 excluded is fine
         E, B = ctx.fields_at(T[-1], x, np.array([4]))
         assert np.all(np.isfinite(E))
+
+
+@pytest.mark.parametrize("n,depth,m", [(48, 64, 300), (300, 128, 257)])
+def test_midpoint_ablation_matches_oracle(orc, n, depth, m):
+    """The midpoint reconstruction of Eq. (mid) (an accuracy ablation) on
+    accelerating sources: same k*, fields to 1e-12, as the oracle in the same
+    mode."""
+    print(f"case midpoint ablation n={n} depth={depth} m={m}", flush=True)
+    dt = 1e-13
+    T, w, v = bunch.wiggly_history(n, depth, dt, seed=n + 5)
+    rng = np.random.default_rng(m)
+    x = 2e-3 * rng.standard_normal((3, m))
+    try:
+        orc.set_reconstruction(1)
+        E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], x, None, want_kstar=True, want_abs=True)
+    finally:
+        orc.set_reconstruction(0)
+    El, Bl = orc.fields(T, w, v, Q, T[-1], x, None)
+    g = 1 / np.sqrt(1 - (v[-1] ** 2).sum(0) / bunch.C_LIGHT**2)
+    with _ctx(n, depth, dt, recon=1) as ctx:
+        ctx.set_history(T, w, v, v[-1] * g)
+        E, B, k = ctx.fields_at(T[-1], x, want_kstar=True)
+    assert_kstar("midpoint", k, k0)
+    assert_fields("midpoint", E, B, E0, B0, SE, SB)
+    diff = np.max(np.linalg.norm(E0 - El, axis=0)) / np.sqrt(np.mean((El**2).sum(0)))
+    print(f"   midpoint vs linear reconstruction: max |dE| / rms E = {diff:.2e}", flush=True)
+    assert diff > 1e-9  # the ablation changes the fields
