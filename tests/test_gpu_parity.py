@@ -234,3 +234,25 @@ def test_midpoint_ablation_matches_oracle(orc, n, depth, m):
     diff = np.max(np.linalg.norm(E0 - El, axis=0)) / np.sqrt(np.mean((El**2).sum(0)))
     print(f"   midpoint vs linear reconstruction: max |dE| / rms E = {diff:.2e}", flush=True)
     assert diff > 1e-9  # the ablation changes the fields
+
+
+def test_c5_full_size_sampled(orc):
+    """C5 size (N=262144, D=1024, dipole at 3 R_E, 17 GB history ring): the
+    step's fields at 256 seeded targets against the oracle, and their k*."""
+    wl = bunch.C5
+    print("case C5 full size sampled", flush=True)
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    n = wl.bunch.n
+    sub = bunch.target_subset(n, 256, 105)
+    T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], r[:, sub], sub, want_kstar=True, want_abs=True)
+    del w, v
+    print(f"   oracle done; before-history fraction {float((k0 < 0).mean()):.3f}", flush=True)
+    with _ctx(n, wl.depth, wl.dt, ext_field=1, dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        _, _, k = ctx.fields_at(0.0, r[:, sub], sub, want_kstar=True)
+        ctx.step(1)
+        Es, Bs = ctx.fields()
+    assert_kstar("C5 subset", k, k0)
+    assert_fields("C5 subset (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
