@@ -72,7 +72,7 @@ def algorithmic_flops(counters):
 SURROGATE_SAMPLES = 50_000_000  # training pairs, half from a C2 bunch, half from this workload's
 
 
-def train_surrogate(ctx, wl, r):
+def train_surrogate(ctx, wl, r, epochs=2):
     """Train the context's surrogate network on pairs drawn from a C2 bunch
     and from this workload's bunch (4 steps in), before any timing."""
     from paper_2605_05543_amd import surrogate
@@ -82,14 +82,14 @@ def train_surrogate(ctx, wl, r):
     ctx.step(4)
     ctx.surrogate_set(bunch.surrogate_init(0), bunch.sigma_ref_of(r))
     s3 = ctx.surrogate_samples_torch(half, seed=23)
-    rep = surrogate.train(ctx, [s2, s3], batch=8192)
+    rep = surrogate.train(ctx, [s2, s3], batch=8192, steps=epochs * (SURROGATE_SAMPLES // 8192))
     del s2, s3
     log(f"  surrogate trained on {SURROGATE_SAMPLES:.1e} pairs: loss {rep['loss_first']:.3e} -> "
         f"{rep['loss_last']:.3e} in {rep['steps']} steps, {rep['seconds']:.2f} s")
     return rep
 
 
-def run_path(wl, r, u, precision, guess, steps, warmup):
+def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2):
     import torch
 
     from paper_2605_05543_amd._lib import Context
@@ -100,7 +100,7 @@ def run_path(wl, r, u, precision, guess, steps, warmup):
                   guess=4 if guess == 4 else 0)
     ctx.init_bunch(r, u, 0.0)
     ctx.init_history_straight()
-    train_rep = train_surrogate(ctx, wl, r) if guess == 1 else None
+    train_rep = train_surrogate(ctx, wl, r, train_epochs) if guess == 1 else None
     ctx.set_mode(precision, guess)
     if guess == 4:
         ctx.step(1)  # the first step bisects and fills the bracket cache
@@ -174,6 +174,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu", action="store_true")
+X
     ap.add_argument("--paths", default="fp64:bisect,mixed:mlp,mixed:bisect,mixed:ballistic,fp64:ballistic,"
                                         "fp64:previous")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -204,7 +205,7 @@ def main():
     results = []
     for spec in args.paths.split(","):
         p, g = spec.split(":")
-        results.append(run_path(wl, r, u, pmap[p], gmap[g], args.steps, args.warmup))
+        results.append(run_path(wl, r, u, pmap[p], gmap[g], args.steps, args.warmup, args.train_epochs))
     plain = results[0]
     # headline: the mixed-precision surrogate-guided path when it was run,
     # else the first mixed path, else the plain FP64 path
