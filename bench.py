@@ -174,7 +174,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu", action="store_true")
-X
+    ap.add_argument("--train-epochs", type=int, default=2, help="passes over the surrogate's training pairs")
     ap.add_argument("--paths", default="fp64:bisect,mixed:mlp,mixed:bisect,mixed:ballistic,fp64:ballistic,"
                                         "fp64:previous")
     ap.add_argument("--calibrate-copy", action="store_true",
