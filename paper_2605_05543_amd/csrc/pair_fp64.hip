@@ -159,6 +159,21 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
     // every logical slot (shared by all sources).
     const int nbuf = p.nbuf;
     double *Ls = reinterpret_cast<double *>(lds + nbuf * S * D);
+    // A tile buffer holds its S * D records as two arrays of 16-byte
+    // halves, {x, y} then {z, L^2}: lanes that probe different slots then
+    // spread over twice as many LDS bank groups as with 32-byte records.
+    struct TileView {
+        const double2 *xy, *zl;
+        __device__ double4 rec(int i) const
+        {
+            const double2 a = xy[i], b = zl[i];
+            return make_double4(a.x, a.y, b.x, b.y);
+        }
+    };
+    auto view = [&](int bi) {
+        const double2 *base = reinterpret_cast<const double2 *>(lds + bi * S * D);
+        return TileView{base, base + S * D};
+    };
     // the present time is the newest slot's (the clock lives in T)
     const double tnow = p.T[p.head];
     for (int b = tid; b < D; b += kBlock) {
@@ -181,26 +196,24 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
         }
         return w;
     };
-    auto put = [&](double4 *buf, int ns, int q, double4 w) {
+    auto put = [&](int bi, int ns, int q, double4 w) {
         int s = S == 2 && q >= D ? 1 : 0;
         int b = q - s * D;
         if (b < D && s < ns) {
             double L = Ls[b];
-            w.w = L * L;
-            buf[s * D + b] = w;
+            double2 *xy = reinterpret_cast<double2 *>(lds + bi * S * D);
+            xy[s * D + b] = make_double2(w.x, w.y);
+            xy[S * D + s * D + b] = make_double2(w.z, L * L);
         }
     };
-    auto stage = [&](double4 *buf, int64_t jt, int ns, double4 r0, double4 r1) {
-        put(buf, ns, tid, r0);
-        put(buf, ns, tid + kBlock, r1);
+    auto stage = [&](int bi, int64_t jt, int ns, double4 r0, double4 r1) {
+        put(bi, ns, tid, r0);
+        put(bi, ns, tid + kBlock, r1);
         for (int q = tid + 2 * kBlock; q < ns * D; q += kBlock) {
             int s = q / D, b = q - (q / D) * D;
             int ph = p.head - b;
             ph += ph < 0 ? D : 0;
-            double4 w = p.ring_w[(jt + s) * D + ph];
-            double L = Ls[b];
-            w.w = L * L;
-            buf[s * D + b] = w;
+            put(bi, ns, q, p.ring_w[(jt + s) * D + ph]);
         }
     };
     auto tile_size = [&](int64_t jt) { return (int)((j1 - jt) < S ? (j1 - jt) : S); };
@@ -215,7 +228,7 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
     // search, with a barrier on either side.
     if (nbuf == 2 && j0 < j1) {
         __syncthreads();
-        stage(lds, j0, tile_size(j0), pf0, pf1);
+        stage(0, j0, tile_size(j0), pf0, pf1);
         if (j0 + S < j1) {
             pf0 = fetch(j0 + S, tile_size(j0 + S), tid);
             pf1 = fetch(j0 + S, tile_size(j0 + S), tid + kBlock);
@@ -241,11 +254,11 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
             if (jt + S < j1)
                 load_brackets(jt + S);
         }
-        double4 *cur = lds;
+        const int cb = nbuf == 2 ? (it & 1) : 0;
+        const TileView cur = view(cb);
         if (nbuf == 2) {
-            cur = lds + (it & 1) * (S * D);
             if (jt + S < j1) {
-                stage(lds + ((it + 1) & 1) * (S * D), jt + S, tile_size(jt + S), pf0, pf1);
+                stage(cb ^ 1, jt + S, tile_size(jt + S), pf0, pf1);
                 if (jt + 2 * S < j1) {
                     pf0 = fetch(jt + 2 * S, tile_size(jt + 2 * S), tid);
                     pf1 = fetch(jt + 2 * S, tile_size(jt + 2 * S), tid + kBlock);
@@ -253,7 +266,7 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
             }
         } else {
             __syncthreads();
-            stage(lds, jt, ns, pf0, pf1);
+            stage(0, jt, ns, pf0, pf1);
             __syncthreads();
             if (jt + S < j1) {
                 pf0 = fetch(jt + S, tile_size(jt + S), tid);
@@ -271,7 +284,7 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                 if (KSTAR && s < ns && jj[s] == self)
                     p.kstar[a * p.n_src + jj[s]] = 0;
                 // a target on the source's present position: eta = 0
-                double4 wn = cur[s * D];
+                double4 wn = cur.rec(s * D);
                 if (valid[s] && rx == wn.x && ry == wn.y && rz == wn.z) {
                     if (!failed)
                         fail_j = (int32_t)jj[s];
@@ -287,16 +300,19 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                 int ph1 = p.head - bb;
                 ph1 += ph1 < 0 ? D : 0;
                 int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
-                v1 = p.ring_v[jj[s] * D + ph1];
-                v2 = p.ring_v[jj[s] * D + ph2];  // unused (inv_h = 0) out of history
+                // uniform row base plus 32-bit lane offsets
+                const char *row = reinterpret_cast<const char *>(p.ring_v + jj[s] * D);
+                v1 = *reinterpret_cast<const double4 *>(row + (uint32_t)ph1 * (uint32_t)sizeof(double4));
+                // unused (inv_h = 0) out of history
+                v2 = *reinterpret_cast<const double4 *>(row + (uint32_t)ph2 * (uint32_t)sizeof(double4));
             };
             auto finish = [&](int s, int b, double4 v1, double4 v2) {
                 const bool before = b < 0;
                 const int bb = before ? D - 1 : b;
                 double f[6], en;
                 double3 vr;
-                bool ok = lw_pair(rx, ry, rz, cur[s * D + bb], Ls[bb], v1, v2, before, p.kq, f, en, vr, MID,
-                                  MID ? cur[s * D + (bb > 0 ? bb - 1 : 0)] : make_double4(0.0, 0.0, 0.0, 0.0));
+                bool ok = lw_pair(rx, ry, rz, cur.rec(s * D + bb), Ls[bb], v1, v2, before, p.kq, f, en, vr, MID,
+                                  MID ? cur.rec(s * D + (bb > 0 ? bb - 1 : 0)) : make_double4(0.0, 0.0, 0.0, 0.0));
                 if (valid[s]) {
                     if (ok) {
 #pragma unroll
@@ -331,11 +347,11 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                     // LDS byte address of the record of xb: f(xb) <= 0, the
                     // bracket lies in (xb, xb + n]
                     uint32_t xo[S];
-                    const uint32_t cur0 = (uint32_t)(cur - lds);
+                    const uint32_t cur0 = (uint32_t)(cb * S * D);  // first record of the buffer
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        inside[s] = lightcone_positive(cur[s * D + D - 1], rx, ry, rz);
-                        xo[s] = lds_base + (cur0 + (uint32_t)(s * D)) * (uint32_t)sizeof(double4);
+                        inside[s] = lightcone_positive(cur.rec(s * D + D - 1), rx, ry, rz);
+                        xo[s] = lds_base + cur0 * (uint32_t)sizeof(double4) + (uint32_t)(s * D) * (uint32_t)sizeof(double2);
                     }
                     bool any = false;
 #pragma unroll
@@ -343,15 +359,17 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                         any = any || (inside[s] && valid[s]);
                     if (__any(any)) {
                         // halving widths depend on D only: uniform across lanes
+                        const uint32_t zl_off = (uint32_t)(S * D) * (uint32_t)sizeof(double2);
                         for (int n = D - 1; n > 1;) {
                             const int half = n >> 1;
-                            const uint32_t hb = (uint32_t)half * (uint32_t)sizeof(double4);
+                            const uint32_t hb = (uint32_t)half * (uint32_t)sizeof(double2);
 #pragma unroll
                             for (int s = 0; s < S; ++s) {
                                 const uint32_t mo = xo[s] + hb;
-                                typedef double dv4 __attribute__((ext_vector_type(4)));
-                                const dv4 v = *(const __attribute__((address_space(3))) dv4 *)(uintptr_t)mo;
-                                const double4 rec = make_double4(v.x, v.y, v.z, v.w);
+                                typedef double dv2 __attribute__((ext_vector_type(2)));
+                                const dv2 va = *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)mo;
+                                const dv2 vb = *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)(mo + zl_off);
+                                const double4 rec = make_double4(va.x, va.y, vb.x, vb.y);
                                 xo[s] = lightcone_positive(rec, rx, ry, rz) ? xo[s] : mo;
                             }
                             n -= half;
@@ -359,7 +377,8 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                     }
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        bk[s] = inside[s] ? (int)((xo[s] - lds_base) / (uint32_t)sizeof(double4) - cur0) - s * D + 1
+                        bk[s] = inside[s] ? (int)((xo[s] - lds_base - cur0 * (uint32_t)sizeof(double4)) /
+                                                  (uint32_t)sizeof(double2)) - s * D + 1
                                           : -1;
                         if (COUNT && valid[s])
                             probes += inside[s] ? 1 + p.nit : 1;
@@ -378,8 +397,8 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                         const bool was_before = g == kBracketBefore;
                         const bool in_range = g >= 1 && g < D;
                         const int ga = in_range ? g : D - 1;  // 1 <= ga <= D - 1
-                        const bool fa = lightcone_positive(cur[s * D + ga], rx, ry, rz);
-                        const bool fb = lightcone_positive(cur[s * D + ga - 1], rx, ry, rz);
+                        const bool fa = lightcone_positive(cur.rec(s * D + ga), rx, ry, rz);
+                        const bool fb = lightcone_positive(cur.rec(s * D + ga - 1), rx, ry, rz);
                         hit[s] = was_before ? !fa : (in_range && fa && !fb);
                         // a bracket index leaves this block only if it is
                         // one (the entry of an excluded pair is never
@@ -390,8 +409,7 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                     }
                     for (int s = 0; s < S; ++s) {
                         if (!hit[s] && valid[s]) {
-                            const double4 *rec = cur + s * D;
-                            auto test = [&](int bb) { return lightcone_positive(rec[bb], rx, ry, rz); };
+                            auto test = [&](int bb) { return lightcone_positive(cur.rec(s * D + bb), rx, ry, rz); };
                             const int g = kcur[s];
                             int fb = 0;
                             bk[s] = search_guided(test, D, g == kBracketBefore || g >= D ? (float)(D - 1) : (float)g, 6,
@@ -419,9 +437,8 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                 for (int s = 0; s < S; ++s) {
                     int b = -1;
                     if (valid[s]) {
-                        const double4 *rec = cur + s * D;
-                        auto test = [&](int bb) { return lightcone_positive(rec[bb], rx, ry, rz); };
-                        double4 wn = rec[0];
+                        auto test = [&](int bb) { return lightcone_positive(cur.rec(s * D + bb), rx, ry, rz); };
+                        double4 wn = cur.rec(s * D);
                         float g;
                         if (GUESS == 2) {
                             double4 vn = p.ring_v[jj[s] * D + p.head];
