@@ -151,7 +151,7 @@ def cpu_baseline(wl, r, u, target_seconds=15.0):
     n = wl.bunch.n
     T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
     threads = orc.max_threads()
-    probe = bunch.target_subset(n, 8, 1001)
+    probe = bunch.target_subset(n, 4 * threads, 1001)  # every thread busy in the rate probe
     t0 = time.perf_counter()
     orc.fields(T, w, v, -bunch.E_CHARGE, T[-1], r[:, probe], probe)
     rate = len(probe) / (time.perf_counter() - t0)
