@@ -107,3 +107,21 @@ def test_mixed_c1_free_running_position_error(orc):
     du = np.max(np.abs(ug - run.u)) / np.max(np.abs(run.u))
     print(f"mixed C1 200 steps: max|dy|/sigma {dy:.2e}, max|du|/|u| {du:.2e}", flush=True)
     assert dy < 1e-9 and du < 1e-9
+
+
+def test_mixed_c3_size_accelerating_history(orc):
+    """Mixed precision at C3 size on curving histories (every segment
+    accelerates): k* exact, fields within 1e-5 of the rms field."""
+    print("case mixed C3 size, accelerating history", flush=True)
+    n, depth, dt = 65536, 512, 1e-13
+    T, w, v = bunch.wiggly_history(n, depth, dt, beta=0.9, sigma=1e-3, accel_rel=0.05, seed=33)
+    g = 1 / np.sqrt(1 - (v[-1] ** 2).sum(0) / bunch.C_LIGHT**2)
+    sub = bunch.target_subset(n, 128, 104)
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], w[-1][:, sub], sub, want_kstar=True, want_abs=True)
+    with _ctx(n, depth, dt) as ctx:
+        ctx.set_history(T, w, v, v[-1] * g)
+        _, _, k = ctx.fields_at(T[-1], w[-1][:, sub], sub, want_kstar=True)
+        ctx.step(1)
+        Es, Bs = ctx.fields()
+    assert_kstar("mixed C3 accelerating", k, k0)
+    assert_mixed("mixed C3 accelerating (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)

@@ -256,3 +256,23 @@ def test_c5_full_size_sampled(orc):
         Es, Bs = ctx.fields()
     assert_kstar("C5 subset", k, k0)
     assert_fields("C5 subset (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
+
+
+def test_c3_size_accelerating_history(orc):
+    """C3 size (N=65536, D=512) on curving histories (acceleration in every
+    segment, pairs in and before the history): the step's fields at 128
+    seeded targets and their k* against the oracle."""
+    print("case C3 size, accelerating history", flush=True)
+    n, depth, dt = 65536, 512, 1e-13
+    T, w, v = bunch.wiggly_history(n, depth, dt, beta=0.9, sigma=1e-3, accel_rel=0.05, seed=33)
+    g = 1 / np.sqrt(1 - (v[-1] ** 2).sum(0) / bunch.C_LIGHT**2)
+    sub = bunch.target_subset(n, 128, 104)
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], w[-1][:, sub], sub, want_kstar=True, want_abs=True)
+    with _ctx(n, depth, dt) as ctx:
+        ctx.set_history(T, w, v, v[-1] * g)
+        _, _, k = ctx.fields_at(T[-1], w[-1][:, sub], sub, want_kstar=True)
+        ctx.step(1)
+        Es, Bs = ctx.fields()
+    print(f"   before-history fraction {float((k0 < 0).mean()):.3f}", flush=True)
+    assert_kstar("C3 accelerating", k, k0)
+    assert_fields("C3 accelerating (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
