@@ -142,9 +142,15 @@ int splits_for(const empp_config &c)
 {
     if (c.source_splits > 0)
         return std::min(c.source_splits, kMaxSplits);
-    int64_t bx = (c.n + kBlock - 1) / kBlock;
+    // About 8192 blocks of the FP64 pair kernel (32 rounds of one block per
+    // CU) evens out blocks that finish early and keeps each chunk's
+    // histories near its XCD's L2 (measured optimum at N = 65536: 128
+    // chunks); the warm-started search, with less work per tile, does best
+    // with half as many.
+    int64_t bx = (c.n + kBlockFp64 - 1) / kBlockFp64;
     int tile = tile_for_depth(c.depth);
-    int64_t want = (2048 + bx - 1) / bx;
+    const int64_t target = c.guess == EMPP_GUESS_PREVIOUS ? 4096 : 8192;
+    int64_t want = (target + bx - 1) / bx;
     int64_t maxs = std::max<int64_t>(1, c.n / (4 * tile));
     int64_t s = std::min(want, maxs);
     return (int)std::max<int64_t>(1, std::min<int64_t>(s, kMaxSplits));

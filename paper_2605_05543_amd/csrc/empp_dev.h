@@ -14,7 +14,10 @@ constexpr double kMU0 = 1.25663706212e-6;
 #ifndef EMPP_PAIR_BLOCK
 #define EMPP_PAIR_BLOCK 512
 #endif
-constexpr int kBlock = EMPP_PAIR_BLOCK;  // threads per block of the pair kernels
+constexpr int kBlock = EMPP_PAIR_BLOCK;  // threads per block of the mixed pair kernel and per-particle kernels
+// Threads per block of the FP64 pair kernel: 1024 targets share each staged
+// history tile (one block per CU at 128 registers per lane).
+constexpr int kBlockFp64 = 1024;
 constexpr int kMaxSplits = 1024;   // source chunks of one launch
 
 // History layout in HBM (library-owned workspace):

@@ -1,11 +1,11 @@
 // pair_fp64.hip -- all-pairs Lienard-Wiechert field evaluation in double
 // precision (Secs. 2.1-2.2 of arXiv 2605.05543).
 //
-// One thread owns one target.  A block of kBlock (512) targets walks its
+// One thread owns one target.  A block of kBlockFp64 (1024) targets walks its
 // chunk of sources in tiles of S sources: the tile's histories (positions
 // plus the light distance c (t - T_k) of every slot) are staged once into
 // LDS and every target of the block then searches them, so each history
-// byte read from L2/HBM serves 512 targets.  The S searches of a tile run in
+// byte read from L2/HBM serves 1024 targets.  The S searches of a tile run in
 // lockstep (a fixed number of bisection steps, no divergence), so S
 // independent LDS chains are in flight per lane; then the 2 S bracket
 // velocity records are fetched together and the S pair fields evaluated.
@@ -107,17 +107,17 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
 }  // namespace
 
 template <bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID = false>
-__global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
+__global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
 {
     extern __shared__ double4 lds[];
     // LDS address of the dynamic buffer (32-bit, for offset arithmetic)
     const uint32_t lds_base = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)lds;
     const int D = p.D;
     const int tid = threadIdx.x;
-    const int nbx = (int)((p.m + kBlock - 1) / kBlock);
+    const int nbx = (int)((p.m + kBlockFp64 - 1) / kBlockFp64);
     int bxi, split;
     pair_block_coords(nbx, p.nsplit, bxi, split);
-    const int64_t a = (int64_t)bxi * kBlock + tid;
+    const int64_t a = (int64_t)bxi * kBlockFp64 + tid;
     const bool active = a < p.m;
     const int64_t j0 = (int64_t)split * p.src_per_split;
     int64_t j1 = j0 + p.src_per_split;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
     };
     // the present time is the newest slot's (the clock lives in T)
     const double tnow = p.T[p.head];
-    for (int b = tid; b < D; b += kBlock) {
+    for (int b = tid; b < D; b += kBlockFp64) {
         int ph = p.head - b;
         ph += ph < 0 ? D : 0;
         Ls[b] = kC_LIGHT * (tnow - p.T[ph]);
@@ -208,8 +208,8 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
     };
     auto stage = [&](int bi, int64_t jt, int ns, double4 r0, double4 r1) {
         put(bi, ns, tid, r0);
-        put(bi, ns, tid + kBlock, r1);
-        for (int q = tid + 2 * kBlock; q < ns * D; q += kBlock) {
+        put(bi, ns, tid + kBlockFp64, r1);
+        for (int q = tid + 2 * kBlockFp64; q < ns * D; q += kBlockFp64) {
             int s = q / D, b = q - (q / D) * D;
             int ph = p.head - b;
             ph += ph < 0 ? D : 0;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
     double4 pf0 = make_double4(0.0, 0.0, 0.0, 0.0), pf1 = pf0;
     if (j0 < j1) {
         pf0 = fetch(j0, tile_size(j0), tid);
-        pf1 = fetch(j0, tile_size(j0), tid + kBlock);
+        pf1 = fetch(j0, tile_size(j0), tid + kBlockFp64);
     }
     // Two buffers: tile i + 1 is written while tile i is searched, and one
     // barrier per tile both publishes tile i + 1 and retires tile i's
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
         stage(0, j0, tile_size(j0), pf0, pf1);
         if (j0 + S < j1) {
             pf0 = fetch(j0 + S, tile_size(j0 + S), tid);
-            pf1 = fetch(j0 + S, tile_size(j0 + S), tid + kBlock);
+            pf1 = fetch(j0 + S, tile_size(j0 + S), tid + kBlockFp64);
         }
         __syncthreads();
     }
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
                 stage(cb ^ 1, jt + S, tile_size(jt + S), pf0, pf1);
                 if (jt + 2 * S < j1) {
                     pf0 = fetch(jt + 2 * S, tile_size(jt + 2 * S), tid);
-                    pf1 = fetch(jt + 2 * S, tile_size(jt + 2 * S), tid + kBlock);
+                    pf1 = fetch(jt + 2 * S, tile_size(jt + 2 * S), tid + kBlockFp64);
                 }
             }
         } else {
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
             __syncthreads();
             if (jt + S < j1) {
                 pf0 = fetch(jt + S, tile_size(jt + S), tid);
-                pf1 = fetch(jt + S, tile_size(jt + S), tid + kBlock);
+                pf1 = fetch(jt + S, tile_size(jt + S), tid + kBlockFp64);
             }
         }
         if (active) {
@@ -526,12 +526,12 @@ __global__ __launch_bounds__(kBlock, 4) void pair_fp64_kernel(PairParams p)
 int pair_fp64_tile(int D) { return D <= 1024 ? 2 : 1; }
 
 // LDS buffers: two (staging overlapped with the search) while two tiles
-// and the light distances fit in 80 KiB, so that two 512-thread blocks
-// share a CU; else one.
+// and the light distances fit in the CU's 160 KiB (one 1024-thread block
+// per CU), else one.
 int pair_fp64_nbuf(int D, int tile)
 {
     size_t two = 2 * (size_t)tile * D * sizeof(double4) + (size_t)D * sizeof(double);
-    return two <= 80 * 1024 ? 2 : 1;
+    return two <= 160 * 1024 ? 2 : 1;
 }
 
 // Host-side launcher (called from the C ABI layer).
@@ -541,7 +541,7 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
     if (p.ad || p.recon == 1)
         p.tile = 1;  // the adaptive reductions and the midpoint ablation use one-source tiles
     p.nbuf = pair_fp64_nbuf(p.D, p.tile);
-    const int64_t nblocks = (p.m + kBlock - 1) / kBlock * p.nsplit;
+    const int64_t nblocks = (p.m + kBlockFp64 - 1) / kBlockFp64 * p.nsplit;
     if (nblocks < 1 || nblocks > INT32_MAX)
         return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nblocks);
@@ -551,14 +551,14 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
         if (lds > 65536)                                                                                    \
             (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, C, G, S, A>,                        \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-        hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S, A>), grid, dim3(kBlock), lds, stream, p);          \
+        hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S, A>), grid, dim3(kBlockFp64), lds, stream, p);          \
     } while (0)
 #define EMPP_LAUNCH_MID(K)                                                                                   \
     do {                                                                                                    \
         if (lds > 65536)                                                                                    \
             (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, false, 0, 1, false, true>,          \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-        hipLaunchKernelGGL((pair_fp64_kernel<K, false, 0, 1, false, true>), grid, dim3(kBlock), lds, stream, p); \
+        hipLaunchKernelGGL((pair_fp64_kernel<K, false, 0, 1, false, true>), grid, dim3(kBlockFp64), lds, stream, p); \
     } while (0)
 #define EMPP_BY_TILE(K, C, G, A) \
     do { if (p.tile == 2) EMPP_LAUNCH(K, C, G, 2, A); else EMPP_LAUNCH(K, C, G, 1, A); } while (0)
