@@ -38,7 +38,14 @@ def test_workspace_size_and_validation():
     cfg = _lib.Config(n=65536, depth=512, q=-1.602176634e-19, m=9.1093837015e-31, dt=1e-13)
     nbytes = _lib.empp_workspace_size(cfg)
     ring = 65536 * 512 * 32 * 2
-    assert ring <= nbytes < ring + 200 * 2**20
+    # the ring plus the per-chunk partials (at most 128 chunks x 12 doubles
+    # per target) and small per-particle arrays
+    partials = 128 * 12 * 65536 * 8
+    assert ring + partials <= nbytes < ring + partials + 64 * 2**20
+    # the warm-start cache adds N*N uint16 brackets
+    cfg.guess = _lib.EMPP_GUESS_PREVIOUS
+    warm = _lib.empp_workspace_size(cfg)
+    assert ring + 65536 * 65536 * 2 <= warm < nbytes + 65536 * 65536 * 2
     for bad in (dict(n=1), dict(depth=1), dict(depth=5000), dict(dt=0.0), dict(dt=float("nan")), dict(m=-1.0),
                 dict(ext_field=3), dict(precision=7), dict(guess=9)):
         c = _lib.Config(n=64, depth=32, q=-1.0, m=1.0, dt=1e-13)
