@@ -18,15 +18,21 @@ __device__ inline double merge_partials(const double *part, int nsplit, int64_t 
     return s + c;
 }
 
+// One thread per (component, target): the six field components of a
+// target are merged by six threads, which keeps enough loads in flight
+// for the nsplit x 12 x m partials.
 __global__ void merge_fields_kernel(const double *part, int nsplit, int64_t m, double *E, double *B)
 {
-    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= m)
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 6 * m)
         return;
-    for (int k = 0; k < 3; ++k) {
-        E[k * m + a] = merge_partials(part, nsplit, m, k, a);
-        B[k * m + a] = merge_partials(part, nsplit, m, 3 + k, a);
-    }
+    const int k = (int)(idx / m);
+    const int64_t a = idx - (int64_t)k * m;
+    const double v = merge_partials(part, nsplit, m, k, a);
+    if (k < 3)
+        E[k * m + a] = v;
+    else
+        B[(k - 3) * m + a] = v;
 }
 
 // Sec. 2.6: B = (mu0/4pi)(3 (M.rhat) rhat - M)/r^3 with M = M0 e_z, written
@@ -100,21 +106,16 @@ __global__ void push_kernel(PushParams p)
     if (i >= p.N)
         return;
     const int D = p.D;
+    // self-fields merged from the pair partials by merge_fields_kernel
     double Ex = 0, Ey = 0, Ez = 0, Bx = 0, By = 0, Bz = 0;
     if (p.self_field) {
-        Ex = merge_partials(p.part, p.nsplit, p.N, 0, i);
-        Ey = merge_partials(p.part, p.nsplit, p.N, 1, i);
-        Ez = merge_partials(p.part, p.nsplit, p.N, 2, i);
-        Bx = merge_partials(p.part, p.nsplit, p.N, 3, i);
-        By = merge_partials(p.part, p.nsplit, p.N, 4, i);
-        Bz = merge_partials(p.part, p.nsplit, p.N, 5, i);
+        Ex = p.E[i];
+        Ey = p.E[p.N + i];
+        Ez = p.E[2 * p.N + i];
+        Bx = p.B[i];
+        By = p.B[p.N + i];
+        Bz = p.B[2 * p.N + i];
     }
-    p.E[i] = Ex;
-    p.E[p.N + i] = Ey;
-    p.E[2 * p.N + i] = Ez;
-    p.B[i] = Bx;
-    p.B[p.N + i] = By;
-    p.B[2 * p.N + i] = Bz;
     double4 y = p.ring_w[i * D + p.head];
     if (p.ext_field == 1) {
         double gx, gy, gz;
@@ -375,13 +376,19 @@ hipError_t launch_transport(const TransportParams &p, hipStream_t s)
 
 hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, double *E, double *B, hipStream_t s)
 {
-    hipLaunchKernelGGL(merge_fields_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, part, nsplit, m,
-                       E, B);
+    hipLaunchKernelGGL(merge_fields_kernel, dim3((unsigned)((6 * m + 255) / 256)), dim3(256), 0, s, part, nsplit,
+                       m, E, B);
     return hipGetLastError();
 }
 
+// Merge of the self-field partials into E, B, then the push.
 hipError_t launch_push(const PushParams &p, hipStream_t s)
 {
+    if (p.self_field) {
+        hipError_t e = launch_merge_fields(p.part, p.nsplit, p.N, p.E, p.B, s);
+        if (e != hipSuccess)
+            return e;
+    }
     hipLaunchKernelGGL(push_kernel, dim3((unsigned)((p.N + 255) / 256)), dim3(256), 0, s, p);
     return hipGetLastError();
 }
