@@ -95,13 +95,20 @@ __device__ __forceinline__ s4 lds_s4(const unsigned short *p)
     return r;
 }
 
+// Four floats to bf16 (round to nearest even) with the gfx950 packed
+// conversion instruction (v_cvt_pk_bf16_f32), two values per instruction.
 __device__ __forceinline__ s4 pack4(float a, float b, float c, float d)
 {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+    const b2v lo = __builtin_convertvector((f2v){a, b}, b2v);
+    const b2v hi = __builtin_convertvector((f2v){c, d}, b2v);
+    const uint32_t ul = __builtin_bit_cast(uint32_t, lo), uh = __builtin_bit_cast(uint32_t, hi);
     s4 r;
-    r[0] = (short)bf16_bits(a);
-    r[1] = (short)bf16_bits(b);
-    r[2] = (short)bf16_bits(c);
-    r[3] = (short)bf16_bits(d);
+    r[0] = (short)(ul & 0xffffu);
+    r[1] = (short)(ul >> 16);
+    r[2] = (short)(uh & 0xffffu);
+    r[3] = (short)(uh >> 16);
     return r;
 }
 
@@ -187,6 +194,62 @@ __device__ __forceinline__ s4 feature_operand(const float *row_features /* 10 va
         v[r] = k < kIn ? row_features[k] : 0.0f;
     }
     return pack4(v[0], v[1], v[2], v[3]);
+}
+
+// Inference forward of T row tiles (16 rows each) held by one wavefront:
+// every A fragment of W1 and W2 read from LDS feeds T matrix-core products,
+// so the LDS traffic per row falls by T.  Returns z of row l % 16 of tile t
+// in z[t] (valid in every lane).
+template <int T>
+__device__ __forceinline__ void net_forward_tiles(const NetLds &s, const s4 xb[T], float z[T])
+{
+    const int l = threadIdx.x & 63;
+    const int g = l >> 4, col = l & 15;
+    s4 h1[T][8];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        s4 a = lds_s4(&s.W1[(mt * 16 + col) * kW1S + 4 * g]);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            f4 d = mfma16(a, xb[t], f4{0, 0, 0, 0});
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                v[r] = silu_fast(d[r] + s.b1[mt * 16 + 4 * g + r]);
+            h1[t][mt] = pack4(v[0], v[1], v[2], v[3]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+        z[t] = 0.0f;
+#pragma unroll 2
+    for (int mt = 0; mt < 8; ++mt) {
+        f4 acc[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+            acc[t] = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int kt = 0; kt < 8; ++kt) {
+            s4 a = lds_s4(&s.W2[(mt * 16 + col) * kW2S + kt * 16 + 4 * g]);
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                acc[t] = mfma16(a, h1[t][kt], acc[t]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = mt * 16 + 4 * g + r;
+            const float b2 = s.b2[j], w3 = s.W3[j];
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                z[t] += w3 * silu_fast(acc[t][r] + b2);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        z[t] += __shfl_xor(z[t], 16);
+        z[t] += __shfl_xor(z[t], 32);
+        z[t] += s.b3;
+    }
 }
 
 }  // namespace
@@ -509,8 +572,12 @@ __global__ void mlp_sample_kernel(SampleParams p, const int64_t *tgt, const int6
 // consecutive targets in the spatial order, source) with the group's
 // centroid as target, written as the predicted g; the pair kernel scales
 // it by each target's own distance to the source's newest position.
+#ifndef EMPP_GUESS_TILES
+#define EMPP_GUESS_TILES 2
+#endif
 __global__ __launch_bounds__(256) void mlp_group_guess_kernel(const MlpPacked *net, GuessParams p, float *G)
 {
+    constexpr int kTiles = EMPP_GUESS_TILES;  // row tiles per wavefront and pass
     __shared__ NetLds s;
     load_net(s, net);
     __syncthreads();
@@ -521,48 +588,60 @@ __global__ __launch_bounds__(256) void mlp_group_guess_kernel(const MlpPacked *n
     h4 += h4 < 0 ? D : 0;
     const double inv_c = 1.0 / kC_LIGHT;
     const double inv_span = 1.0 / (kC_LIGHT * (p.T[h] - p.T[h4]));
-    for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * 16; base < rows; base += (int64_t)gridDim.x * 64) {
-        int64_t row = base + (l & 15);
-        float f[kIn];
-        if (row < rows) {
-            // source-major rows: a tile of 16 rows shares one source
-            int64_t j = row / p.ngroups, grp = row - j * p.ngroups;
-            double3 cen = p.centroid[grp];
-            double4 wn = p.ring_w[j * D + h];
-            double4 vn = p.ring_v[j * D + h];
-            double4 w4 = p.ring_w[j * D + h4];
-            f[0] = (float)((cen.x - wn.x) * p.inv_sigma);
-            f[1] = (float)((cen.y - wn.y) * p.inv_sigma);
-            f[2] = (float)((cen.z - wn.z) * p.inv_sigma);
-            f[3] = (float)(vn.x * inv_c);
-            f[4] = (float)(vn.y * inv_c);
-            f[5] = (float)(vn.z * inv_c);
-            f[6] = (float)((wn.x - w4.x) * inv_span);
-            f[7] = (float)((wn.y - w4.y) * inv_span);
-            f[8] = (float)((wn.z - w4.z) * inv_span);
-            f[9] = 0.0f;
-        } else {
+    const float sig = (float)(1.0 / p.inv_sigma);
+    for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * 16 * kTiles; base < rows;
+         base += (int64_t)gridDim.x * 64 * kTiles) {
+        s4 xb[kTiles];
+        float gb[kTiles];  // straight-line delay ratio at the centroid (ratio mode)
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t) {
+            const int64_t row = base + t * 16 + (l & 15);
+            float f[kIn];
 #pragma unroll
             for (int k = 0; k < kIn; ++k)
                 f[k] = 0.0f;
-        }
-        FwdState st;
-        float zz = net_forward<false>(s, feature_operand(f), st);
-        if (l < 16 && row < rows) {
-            float g = __expf(zz);
+            if (row < rows) {
+                // source-major rows: a tile of 16 rows shares one source
+                int64_t j = row / p.ngroups, grp = row - j * p.ngroups;
+                double3 cen = p.centroid[grp];
+                double4 wn = p.ring_w[j * D + h];
+                double4 vn = p.ring_v[j * D + h];
+                double4 w4 = p.ring_w[j * D + h4];
+                f[0] = (float)((cen.x - wn.x) * p.inv_sigma);
+                f[1] = (float)((cen.y - wn.y) * p.inv_sigma);
+                f[2] = (float)((cen.z - wn.z) * p.inv_sigma);
+                f[3] = (float)(vn.x * inv_c);
+                f[4] = (float)(vn.y * inv_c);
+                f[5] = (float)(vn.z * inv_c);
+                f[6] = (float)((wn.x - w4.x) * inv_span);
+                f[7] = (float)((wn.y - w4.y) * inv_span);
+                f[8] = (float)((wn.z - w4.z) * inv_span);
+            }
+            xb[t] = feature_operand(f);
+            gb[t] = 1.0f;
             if (p.ratio) {
-                // straight-line look-back from the centroid, in units of
-                // |centroid - w_n| (f[0..2] are that offset over sigma)
-                const float sig = (float)(1.0 / p.inv_sigma);
+                // straight-line look-back from the centroid in units of
+                // |centroid - w_n|
                 const float Rx = f[0] * sig, Ry = f[1] * sig, Rz = f[2] * sig;
                 const float R2 = Rx * Rx + Ry * Ry + Rz * Rz;
                 const float rb = Rx * f[3] + Ry * f[4] + Rz * f[5];
                 const float g2 = 1.0f - (f[3] * f[3] + f[4] * f[4] + f[5] * f[5]);
                 const float sb = (rb + sqrtf(rb * rb + g2 * R2)) / g2;
-                const float gb = sb * __builtin_amdgcn_rsqf(R2);
-                g = R2 > 0.0f && gb > 0.0f ? g / gb : 1.0f;
+                const float b = sb * __builtin_amdgcn_rsqf(R2);
+                gb[t] = R2 > 0.0f && b > 0.0f ? b : 0.0f;
             }
-            G[row] = g;
+        }
+        float zz[kTiles];
+        net_forward_tiles<kTiles>(s, xb, zz);
+#pragma unroll
+        for (int t = 0; t < kTiles; ++t) {
+            const int64_t row = base + t * 16 + (l & 15);
+            if (l < 16 && row < rows) {
+                float g = __expf(zz[t]);
+                if (p.ratio)
+                    g = gb[t] > 0.0f ? g / gb[t] : 1.0f;
+                G[row] = g;
+            }
         }
     }
 }
@@ -667,7 +746,7 @@ hipError_t launch_mlp_sample(const SampleParams &p, const int64_t *tgt, const in
 hipError_t launch_mlp_group_guess(const MlpPacked *net, const GuessParams &p, float *G, hipStream_t s)
 {
     int64_t rows = p.ngroups * p.N;
-    int64_t blocks = (rows + 63) / 64;
+    int64_t blocks = (rows + 255) / 256;
     if (blocks > 8192)
         blocks = 8192;
     hipLaunchKernelGGL(mlp_group_guess_kernel, dim3((unsigned)blocks), dim3(256), 0, s, net, p, G);
