@@ -18,6 +18,11 @@ HIPCC_FLAGS = [
     # packed FP32 instructions (v_pk_*_f32) stay off; the compiler emits
     # scalar FP32 instead
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one expression, as the source
+    # writes it: the rounding of a formula then does not depend on the code
+    # around it, so kernels that inline the same field code into different
+    # search loops give bit-identical results
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

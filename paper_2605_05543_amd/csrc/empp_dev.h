@@ -17,7 +17,10 @@ constexpr double kMU0 = 1.25663706212e-6;
 constexpr int kBlock = EMPP_PAIR_BLOCK;  // threads per block of the mixed pair kernel and per-particle kernels
 // Threads per block of the FP64 pair kernel: 1024 targets share each staged
 // history tile (one block per CU at 128 registers per lane).
-constexpr int kBlockFp64 = 1024;
+#ifndef EMPP_FP64_BLOCK
+#define EMPP_FP64_BLOCK 1024
+#endif
+constexpr int kBlockFp64 = EMPP_FP64_BLOCK;
 constexpr int kMaxSplits = 1024;   // source chunks of one launch
 
 // History layout in HBM (library-owned workspace):
@@ -50,6 +53,7 @@ struct PairParams {
     int32_t nsplit;
     int32_t tile;               // sources staged per LDS tile
     int32_t nbuf;               // LDS tile buffers (FP64 kernel: 1 or 2)
+    int32_t groups;             // groups of `tile` sources per staged tile (FP64 kernel)
     double *part;               // [nsplit][12][m] partial (sum, comp)
     int32_t *kstar;             // [m][N] or null
     unsigned long long *err;    // [2]: first failing pair, status bits

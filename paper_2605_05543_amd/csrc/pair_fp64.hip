@@ -2,19 +2,19 @@
 // precision (Secs. 2.1-2.2 of arXiv 2605.05543).
 //
 // One thread owns one target.  A block of kBlockFp64 (1024) targets walks its
-// chunk of sources in tiles of S sources: the tile's histories (positions
-// plus the light distance c (t - T_k) of every slot) are staged once into
-// LDS and every target of the block then searches them, so each history
-// byte read from L2/HBM serves 1024 targets.  The S searches of a tile run in
-// lockstep (a fixed number of bisection steps, no divergence), so S
-// independent LDS chains are in flight per lane; then the 2 S bracket
-// velocity records are fetched together and the S pair fields evaluated.
-// Targets are visited in a spatial (Morton) order so that the lanes of a
-// wavefront probe nearby history slots.  Sums are kept per target in
-// registers: a plain partial over 8 tiles merged into a Neumaier-compensated
-// total; source chunks (grid.y) write (sum, compensation) partials that the
-// push kernel merges in a fixed order, so results do not depend on
-// scheduling.
+// chunk of sources in staged tiles of up to four sources: the tile's
+// histories (positions plus the light distance c (t - T_k) of every slot)
+// are staged once into LDS, double-buffered behind one barrier per tile, and
+// every target of the block then searches them, so each history byte read
+// from L2/HBM serves 1024 targets.  The sources of a tile are searched in
+// groups of S in lockstep (a fixed number of bisection steps, no divergence);
+// then the 2 S bracket velocity records are fetched together and the S pair
+// fields evaluated.  Targets are visited in a spatial (Morton) order so that
+// the lanes of a wavefront probe nearby history slots.  Sums are kept per
+// target in registers: a plain partial over 16 sources merged into a
+// Neumaier-compensated total; source chunks (grid.y) write (sum,
+// compensation) partials that the push kernel merges in a fixed order, so
+// results do not depend on scheduling.
 #include "pair_common.h"
 
 namespace empp {
@@ -149,17 +149,22 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
     }
     double sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    int tiles_in_acc = 0;
+    int groups_in_acc = 0;
     int probes = 0, nbefore = 0, npairs = 0, nfall = 0;
     bool failed = false;
     int32_t fail_j = 0;  // sources number at most 2^31
     const float inv_cdt = (float)(1.0 / (kC_LIGHT * p.dt));
 
-    // LDS: nbuf tile buffers of S * D records, then the light distance of
+    // LDS: nbuf tile buffers of TS * D records, then the light distance of
     // every logical slot (shared by all sources).
     const int nbuf = p.nbuf;
-    double *Ls = reinterpret_cast<double *>(lds + nbuf * S * D);
-    // A tile buffer holds its S * D records as two arrays of 16-byte
+    // A staged tile holds G groups of S sources; the S sources of a group
+    // are searched in lockstep, and one barrier per staged tile serves all
+    // its groups.
+    const int G = p.groups;
+    const int TS = S * G;
+    double *Ls = reinterpret_cast<double *>(lds + nbuf * TS * D);
+    // A tile buffer holds its TS * D records as two arrays of 16-byte
     // halves, {x, y} then {z, L^2}: lanes that probe different slots then
     // spread over twice as many LDS bank groups as with 32-byte records.
     struct TileView {
@@ -170,9 +175,9 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
             return make_double4(a.x, a.y, b.x, b.y);
         }
     };
-    auto view = [&](int bi) {
-        const double2 *base = reinterpret_cast<const double2 *>(lds + bi * S * D);
-        return TileView{base, base + S * D};
+    auto view = [&](int bi, int g) {
+        const double2 *base = reinterpret_cast<const double2 *>(lds + bi * TS * D);
+        return TileView{base + g * S * D, base + TS * D + g * S * D};
     };
     // the present time is the newest slot's (the clock lives in T)
     const double tnow = p.T[p.head];
@@ -184,9 +189,10 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
     // Tile records are prefetched into registers one tile ahead (the first
     // two records of each thread), so their HBM/L2 latency overlaps the
     // previous tile's work; deeper histories load the rest in place.
-    // Record q of a tile: source q / D (q < S D, S <= 2), slot q % D.
+    // Record q of a tile: source q / D (q < TS D, TS <= 4), slot q % D.
+    auto src_of = [&](int q) { return (q >= D) + (q >= 2 * D) + (q >= 3 * D); };
     auto fetch = [&](int64_t jt, int ns, int q) -> double4 {
-        int s = S == 2 && q >= D ? 1 : 0;
+        int s = src_of(q);
         int b = q - s * D;
         double4 w = make_double4(0.0, 0.0, 0.0, 0.0);
         if (b < D && s < ns) {
@@ -197,13 +203,13 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
         return w;
     };
     auto put = [&](int bi, int ns, int q, double4 w) {
-        int s = S == 2 && q >= D ? 1 : 0;
+        int s = src_of(q);
         int b = q - s * D;
         if (b < D && s < ns) {
             double L = Ls[b];
-            double2 *xy = reinterpret_cast<double2 *>(lds + bi * S * D);
+            double2 *xy = reinterpret_cast<double2 *>(lds + bi * TS * D);
             xy[s * D + b] = make_double2(w.x, w.y);
-            xy[S * D + s * D + b] = make_double2(w.z, L * L);
+            xy[TS * D + s * D + b] = make_double2(w.z, L * L);
         }
     };
     auto stage = [&](int bi, int64_t jt, int ns, double4 r0, double4 r1) {
@@ -216,7 +222,7 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
             put(bi, ns, q, p.ring_w[(jt + s) * D + ph]);
         }
     };
-    auto tile_size = [&](int64_t jt) { return (int)((j1 - jt) < S ? (j1 - jt) : S); };
+    auto tile_size = [&](int64_t jt) { return (int)((j1 - jt) < TS ? (j1 - jt) : TS); };
     double4 pf0 = make_double4(0.0, 0.0, 0.0, 0.0), pf1 = pf0;
     if (j0 < j1) {
         pf0 = fetch(j0, tile_size(j0), tid);
@@ -229,9 +235,9 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
     if (nbuf == 2 && j0 < j1) {
         __syncthreads();
         stage(0, j0, tile_size(j0), pf0, pf1);
-        if (j0 + S < j1) {
-            pf0 = fetch(j0 + S, tile_size(j0 + S), tid);
-            pf1 = fetch(j0 + S, tile_size(j0 + S), tid + kBlockFp64);
+        if (j0 + TS < j1) {
+            pf0 = fetch(j0 + TS, tile_size(j0 + TS), tid);
+            pf1 = fetch(j0 + TS, tile_size(j0 + TS), tid + kBlockFp64);
         }
         __syncthreads();
     }
@@ -245,8 +251,28 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
     if (GUESS == 4 && j0 < j1)
         load_brackets(j0);
     int it = 0;
-    for (int64_t jt = j0; jt < j1; jt += S, ++it) {
-        const int ns = tile_size(jt);
+    for (int64_t jts = j0; jts < j1; jts += TS, ++it) {
+        const int cb = nbuf == 2 ? (it & 1) : 0;
+        if (nbuf == 2) {
+            if (jts + TS < j1) {
+                stage(cb ^ 1, jts + TS, tile_size(jts + TS), pf0, pf1);
+                if (jts + 2 * TS < j1) {
+                    pf0 = fetch(jts + 2 * TS, tile_size(jts + 2 * TS), tid);
+                    pf1 = fetch(jts + 2 * TS, tile_size(jts + 2 * TS), tid + kBlockFp64);
+                }
+            }
+        } else {
+            __syncthreads();
+            stage(0, jts, tile_size(jts), pf0, pf1);
+            __syncthreads();
+            if (jts + TS < j1) {
+                pf0 = fetch(jts + TS, tile_size(jts + TS), tid);
+                pf1 = fetch(jts + TS, tile_size(jts + TS), tid + kBlockFp64);
+            }
+        }
+      for (int grp = 0; grp < G && jts + grp * S < j1; ++grp) {
+        const int64_t jt = jts + grp * S;
+        const int ns = (int)((j1 - jt) < S ? (j1 - jt) : S);
         if (GUESS == 4) {
 #pragma unroll
             for (int s = 0; s < S; ++s)
@@ -254,25 +280,7 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
             if (jt + S < j1)
                 load_brackets(jt + S);
         }
-        const int cb = nbuf == 2 ? (it & 1) : 0;
-        const TileView cur = view(cb);
-        if (nbuf == 2) {
-            if (jt + S < j1) {
-                stage(cb ^ 1, jt + S, tile_size(jt + S), pf0, pf1);
-                if (jt + 2 * S < j1) {
-                    pf0 = fetch(jt + 2 * S, tile_size(jt + 2 * S), tid);
-                    pf1 = fetch(jt + 2 * S, tile_size(jt + 2 * S), tid + kBlockFp64);
-                }
-            }
-        } else {
-            __syncthreads();
-            stage(0, jt, ns, pf0, pf1);
-            __syncthreads();
-            if (jt + S < j1) {
-                pf0 = fetch(jt + S, tile_size(jt + S), tid);
-                pf1 = fetch(jt + S, tile_size(jt + S), tid + kBlockFp64);
-            }
-        }
+        const TileView cur = view(cb, grp);
         if (active) {
             bool valid[S];
             int64_t jj[S];
@@ -347,11 +355,13 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
                     // LDS byte address of the record of xb: f(xb) <= 0, the
                     // bracket lies in (xb, xb + n]
                     uint32_t xo[S];
-                    const uint32_t cur0 = (uint32_t)(cb * S * D);  // first record of the buffer
+                    // LDS byte address of the group's first {x, y} half
+                    const uint32_t xy0 = lds_base + (uint32_t)(cb * TS * D) * (uint32_t)sizeof(double4) +
+                                         (uint32_t)(grp * S * D) * (uint32_t)sizeof(double2);
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
                         inside[s] = lightcone_positive(cur.rec(s * D + D - 1), rx, ry, rz);
-                        xo[s] = lds_base + cur0 * (uint32_t)sizeof(double4) + (uint32_t)(s * D) * (uint32_t)sizeof(double2);
+                        xo[s] = xy0 + (uint32_t)(s * D) * (uint32_t)sizeof(double2);
                     }
                     bool any = false;
 #pragma unroll
@@ -359,7 +369,7 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
                         any = any || (inside[s] && valid[s]);
                     if (__any(any)) {
                         // halving widths depend on D only: uniform across lanes
-                        const uint32_t zl_off = (uint32_t)(S * D) * (uint32_t)sizeof(double2);
+                        const uint32_t zl_off = (uint32_t)(TS * D) * (uint32_t)sizeof(double2);
                         for (int n = D - 1; n > 1;) {
                             const int half = n >> 1;
                             const uint32_t hb = (uint32_t)half * (uint32_t)sizeof(double2);
@@ -377,9 +387,7 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
                     }
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        bk[s] = inside[s] ? (int)((xo[s] - lds_base - cur0 * (uint32_t)sizeof(double4)) /
-                                                  (uint32_t)sizeof(double2)) - s * D + 1
-                                          : -1;
+                        bk[s] = inside[s] ? (int)((xo[s] - xy0) / (uint32_t)sizeof(double2)) - s * D + 1 : -1;
                         if (COUNT && valid[s])
                             probes += inside[s] ? 1 + p.nit : 1;
                     }
@@ -466,16 +474,17 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
                 }
             }
         }
-        // plain partial sums over 8 tiles, then one compensated merge (the
-        // same cadence for every search mode: results are bit-identical)
-        if (++tiles_in_acc == 8) {
+        // plain partial sums over 16 sources, then one compensated merge
+        // (the same cadence for every search mode: results are bit-identical)
+        if (++groups_in_acc * S == 16) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
                 neumaier(sum[k], comp[k], acc[k]);
                 acc[k] = 0.0;
             }
-            tiles_in_acc = 0;
+            groups_in_acc = 0;
         }
+      }
         if (nbuf == 2)
             __syncthreads();
     }
@@ -520,10 +529,11 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
     }
 }
 
-// Sources per LDS tile for a history depth: two when two histories fit in
-// 64 KiB, else one (depths up to 4096 use up to 160 KiB with the slot
-// light distances).
-int pair_fp64_tile(int D) { return D <= 1024 ? 2 : 1; }
+// Sources searched in lockstep by a thread.  One source per group with
+// several groups per staged tile measured faster than two in lockstep (at
+// N = 65536, D = 512: 39.0 against 41.3 ms for the bisection): the single
+// search needs fewer registers and the barrier is shared all the same.
+constexpr int kLockstep = 1;
 
 // LDS buffers: two (staging overlapped with the search) while two tiles
 // and the light distances fit in the CU's 160 KiB (one 1024-thread block
@@ -534,18 +544,29 @@ int pair_fp64_nbuf(int D, int tile)
     return two <= 160 * 1024 ? 2 : 1;
 }
 
+// Sources per staged LDS tile for a history depth: as many as keep two
+// buffers within the CU's LDS, at most four (one barrier per staged tile).
+int pair_fp64_tile(int D)
+{
+    for (int ts = 4; ts > 1; --ts)
+        if (pair_fp64_nbuf(D, ts) == 2)
+            return ts;
+    return 1;
+}
+
 // Host-side launcher (called from the C ABI layer).
 hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar, bool count)
 {
     PairParams p = p0;
-    if (p.ad || p.recon == 1)
-        p.tile = 1;  // the adaptive reductions and the midpoint ablation use one-source tiles
-    p.nbuf = pair_fp64_nbuf(p.D, p.tile);
+    const int staged = pair_fp64_tile(p.D);
+    p.tile = kLockstep;
+    p.groups = staged / kLockstep;
+    p.nbuf = pair_fp64_nbuf(p.D, staged);
     const int64_t nblocks = (p.m + kBlockFp64 - 1) / kBlockFp64 * p.nsplit;
     if (nblocks < 1 || nblocks > INT32_MAX)
         return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nblocks);
-    size_t lds = (size_t)p.nbuf * p.tile * p.D * sizeof(double4) + (size_t)p.D * sizeof(double);
+    size_t lds = (size_t)p.nbuf * staged * p.D * sizeof(double4) + (size_t)p.D * sizeof(double);
 #define EMPP_LAUNCH(K, C, G, S, A)                                                                           \
     do {                                                                                                    \
         if (lds > 65536)                                                                                    \
@@ -560,8 +581,7 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
         hipLaunchKernelGGL((pair_fp64_kernel<K, false, 0, 1, false, true>), grid, dim3(kBlockFp64), lds, stream, p); \
     } while (0)
-#define EMPP_BY_TILE(K, C, G, A) \
-    do { if (p.tile == 2) EMPP_LAUNCH(K, C, G, 2, A); else EMPP_LAUNCH(K, C, G, 1, A); } while (0)
+#define EMPP_BY_TILE(K, C, G, A) EMPP_LAUNCH(K, C, G, kLockstep, A)
 #define EMPP_BY_ADAPT(C, G) \
     do { if (p.ad) EMPP_LAUNCH(false, C, G, 1, true); else EMPP_BY_TILE(false, C, G, false); } while (0)
     if (p.ad && (kstar || p.x || p.guess == 1))
