@@ -17,7 +17,14 @@
 // results do not depend on scheduling.
 #include "pair_common.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace empp {
+
+// Records per half-array of a double-buffered LDS tile: 32 KiB of {x, y}
+// halves, then 32 KiB of {z, L^2} halves.
+constexpr int kHalfRecs = 2048;
 
 namespace {
 
@@ -151,22 +158,26 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
     double acc[6] = {0, 0, 0, 0, 0, 0};
     int groups_in_acc = 0;
     int probes = 0, nbefore = 0, npairs = 0, nfall = 0;
-    bool failed = false;
-    int32_t fail_j = 0;  // sources number at most 2^31
+    // first (lowest) source of a failing pair; sources number below 2^31
+    int32_t fail_j = INT32_MAX;
     const float inv_cdt = (float)(1.0 / (kC_LIGHT * p.dt));
 
-    // LDS: nbuf tile buffers of TS * D records, then the light distance of
-    // every logical slot (shared by all sources).
+    // LDS: nbuf tile buffers, then the light distance of every logical slot
+    // (shared by all sources).  A buffer holds its TS * D records as two
+    // arrays of 16-byte halves, {x, y} then {z, L^2}, hrec halves apart:
+    // lanes that probe different slots then spread over twice as many LDS
+    // bank groups as with 32-byte records.  With two buffers the distance is
+    // the fixed kHalfRecs, so a probe's two reads share one address (the
+    // second one at an immediate offset).
     const int nbuf = p.nbuf;
     // A staged tile holds G groups of S sources; the S sources of a group
     // are searched in lockstep, and one barrier per staged tile serves all
     // its groups.
     const int G = p.groups;
     const int TS = S * G;
-    double *Ls = reinterpret_cast<double *>(lds + nbuf * TS * D);
-    // A tile buffer holds its TS * D records as two arrays of 16-byte
-    // halves, {x, y} then {z, L^2}: lanes that probe different slots then
-    // spread over twice as many LDS bank groups as with 32-byte records.
+    const int hrec = nbuf == 2 ? kHalfRecs : TS * D;
+    double2 *const halves = reinterpret_cast<double2 *>(lds);
+    double *Ls = reinterpret_cast<double *>(halves + nbuf * 2 * hrec);
     struct TileView {
         const double2 *xy, *zl;
         __device__ double4 rec(int i) const
@@ -176,8 +187,8 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
         }
     };
     auto view = [&](int bi, int g) {
-        const double2 *base = reinterpret_cast<const double2 *>(lds + bi * TS * D);
-        return TileView{base + g * S * D, base + TS * D + g * S * D};
+        const double2 *base = halves + bi * 2 * hrec + g * S * D;
+        return TileView{base, base + hrec};
     };
     // the present time is the newest slot's (the clock lives in T)
     const double tnow = p.T[p.head];
@@ -207,9 +218,9 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
         int b = q - s * D;
         if (b < D && s < ns) {
             double L = Ls[b];
-            double2 *xy = reinterpret_cast<double2 *>(lds + bi * TS * D);
-            xy[s * D + b] = make_double2(w.x, w.y);
-            xy[TS * D + s * D + b] = make_double2(w.z, L * L);
+            double2 *xy = halves + bi * 2 * hrec + s * D + b;
+            xy[0] = make_double2(w.x, w.y);
+            xy[hrec] = make_double2(w.z, L * L);
         }
     };
     auto stage = [&](int bi, int64_t jt, int ns, double4 r0, double4 r1) {
@@ -294,9 +305,7 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
                 // a target on the source's present position: eta = 0
                 double4 wn = cur.rec(s * D);
                 if (valid[s] && rx == wn.x && ry == wn.y && rz == wn.z) {
-                    if (!failed)
-                        fail_j = (int32_t)jj[s];
-                    failed = true;
+                    fail_j = min(fail_j, (int32_t)jj[s]);
                     valid[s] = false;
                 }
             }
@@ -332,9 +341,7 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
                             dv2_max = fmax(dv2_max, dx * dx + dy * dy + dz * dz);
                         }
                     } else {
-                        if (!failed)
-                            fail_j = (int32_t)jj[s];
-                        failed = true;
+                        fail_j = min(fail_j, (int32_t)jj[s]);
                     }
                     if (KSTAR)
                         p.kstar[a * p.n_src + jj[s]] = before ? -1 : b;
@@ -356,8 +363,8 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
                     // bracket lies in (xb, xb + n]
                     uint32_t xo[S];
                     // LDS byte address of the group's first {x, y} half
-                    const uint32_t xy0 = lds_base + (uint32_t)(cb * TS * D) * (uint32_t)sizeof(double4) +
-                                         (uint32_t)(grp * S * D) * (uint32_t)sizeof(double2);
+                    const uint32_t xy0 =
+                        lds_base + (uint32_t)(cb * 2 * hrec + grp * S * D) * (uint32_t)sizeof(double2);
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
                         inside[s] = lightcone_positive(cur.rec(s * D + D - 1), rx, ry, rz);
@@ -367,9 +374,8 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
 #pragma unroll
                     for (int s = 0; s < S; ++s)
                         any = any || (inside[s] && valid[s]);
-                    if (__any(any)) {
-                        // halving widths depend on D only: uniform across lanes
-                        const uint32_t zl_off = (uint32_t)(TS * D) * (uint32_t)sizeof(double2);
+                    // halving widths depend on D only: uniform across lanes
+                    auto halve = [&](auto zl_off) {
                         for (int n = D - 1; n > 1;) {
                             const int half = n >> 1;
                             const uint32_t hb = (uint32_t)half * (uint32_t)sizeof(double2);
@@ -378,12 +384,19 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
                                 const uint32_t mo = xo[s] + hb;
                                 typedef double dv2 __attribute__((ext_vector_type(2)));
                                 const dv2 va = *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)mo;
-                                const dv2 vb = *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)(mo + zl_off);
+                                const dv2 vb =
+                                    *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)(mo + (uint32_t)zl_off);
                                 const double4 rec = make_double4(va.x, va.y, vb.x, vb.y);
                                 xo[s] = lightcone_positive(rec, rx, ry, rz) ? xo[s] : mo;
                             }
                             n -= half;
                         }
+                    };
+                    if (__any(any)) {
+                        if (nbuf == 2)
+                            halve(std::integral_constant<uint32_t, kHalfRecs * sizeof(double2)>{});
+                        else
+                            halve((uint32_t)hrec * (uint32_t)sizeof(double2));
                     }
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
@@ -497,7 +510,7 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
             out[k * p.m] = sum[k];
             out[(6 + k) * p.m] = comp[k];
         }
-        if (failed)
+        if (fail_j != INT32_MAX)
             report_error(p.err, tgt, fail_j, kErrCoincident);
     }
     if (ADAPT) {
@@ -535,24 +548,21 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
 // search needs fewer registers and the barrier is shared all the same.
 constexpr int kLockstep = 1;
 
-// LDS buffers: two (staging overlapped with the search) while two tiles
-// and the light distances fit in the CU's 160 KiB (one 1024-thread block
-// per CU), else one.
-int pair_fp64_nbuf(int D, int tile)
+// LDS buffers: two of 64 KiB (staging overlapped with the search) while a
+// staged tile fits in kHalfRecs records, else one sized to the tile
+// (depths above 2048; up to 4096 slots use the CU's 160 KiB with the slot
+// light distances).
+int pair_fp64_nbuf(int D, int tile) { return (int64_t)tile * D <= kHalfRecs ? 2 : 1; }
+
+size_t pair_fp64_lds(int D, int tile)
 {
-    size_t two = 2 * (size_t)tile * D * sizeof(double4) + (size_t)D * sizeof(double);
-    return two <= 160 * 1024 ? 2 : 1;
+    const size_t half = pair_fp64_nbuf(D, tile) == 2 ? kHalfRecs : (size_t)tile * D;
+    return (size_t)pair_fp64_nbuf(D, tile) * 2 * half * sizeof(double2) + (size_t)D * sizeof(double);
 }
 
-// Sources per staged LDS tile for a history depth: as many as keep two
-// buffers within the CU's LDS, at most four (one barrier per staged tile).
-int pair_fp64_tile(int D)
-{
-    for (int ts = 4; ts > 1; --ts)
-        if (pair_fp64_nbuf(D, ts) == 2)
-            return ts;
-    return 1;
-}
+// Sources per staged LDS tile for a history depth: as many as fill a
+// buffer of kHalfRecs records, at most four (one barrier per staged tile).
+int pair_fp64_tile(int D) { return D <= kHalfRecs ? std::min(4, kHalfRecs / D) : 1; }
 
 // Host-side launcher (called from the C ABI layer).
 hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar, bool count)
@@ -566,7 +576,7 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
     if (nblocks < 1 || nblocks > INT32_MAX)
         return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nblocks);
-    size_t lds = (size_t)p.nbuf * staged * p.D * sizeof(double4) + (size_t)p.D * sizeof(double);
+    size_t lds = pair_fp64_lds(p.D, staged);
 #define EMPP_LAUNCH(K, C, G, S, A)                                                                           \
     do {                                                                                                    \
         if (lds > 65536)                                                                                    \
