@@ -1,0 +1,691 @@
+// pair_kernel.h -- the all-pairs Lienard-Wiechert pass shared by the FP64
+// and the mixed-precision pair kernels (Secs. 2.1-2.2 of arXiv 2605.05543).
+//
+// One thread owns one target.  A block of kBlockFp64 (1024) targets walks its
+// chunk of sources in staged tiles of up to four sources: the tile's
+// histories (positions plus the light distance c (t - T_k) of every slot)
+// are staged once into LDS, double-buffered behind one barrier per tile, and
+// every target of the block then searches them, so each history byte read
+// from L2/HBM serves 1024 targets.  The sources of a tile are searched in
+// groups of S in lockstep (a fixed number of bisection steps, no divergence);
+// then the 2 S bracket velocity records are fetched together and the S pair
+// fields evaluated.  Targets are visited in a spatial (Morton) order so that
+// the lanes of a wavefront probe nearby history slots.  Sums are kept per
+// target in registers: a plain partial merged into a compensated total
+// (Neumaier in FP64 every 16 sources, Knuth's two-sum in FP32 every 4);
+// source chunks (grid.y) write (sum, compensation) partials that the push
+// kernel merges in a fixed order, so results do not depend on scheduling.
+//
+// Every sign test is the FP64 test of the paper's bracket, in both
+// precisions: the bracket index is bit-identical across paths and search
+// modes.  MIX selects the mixed-precision field evaluation (root,
+// reconstruction and LW terms in FP32 around FP64 coefficients).
+#pragma once
+
+#include "pair_common.h"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace empp {
+
+// Records per half-array of a double-buffered LDS tile: 32 KiB of {x, y}
+// halves, then 32 KiB of {z, L^2} halves.
+constexpr int kHalfRecs = 2048;
+
+// Sources searched in lockstep by a thread.  One source per group with
+// several groups per staged tile measured faster than two in lockstep (at
+// N = 65536, D = 512: 39.0 against 41.3 ms for the bisection): the single
+// search needs fewer registers and the barrier is shared all the same.
+constexpr int kLockstep = 1;
+
+// LDS buffers: two of 64 KiB (staging overlapped with the search) while a
+// staged tile fits in kHalfRecs records, else one sized to the tile
+// (depths above 2048; up to 4096 slots use the CU's 160 KiB with the slot
+// light distances).
+inline int pair_nbuf(int D, int tile) { return (int64_t)tile * D <= kHalfRecs ? 2 : 1; }
+
+inline size_t pair_lds_bytes(int D, int tile)
+{
+    const size_t half = pair_nbuf(D, tile) == 2 ? kHalfRecs : (size_t)tile * D;
+    return (size_t)pair_nbuf(D, tile) * 2 * half * sizeof(double2) + (size_t)D * sizeof(double);
+}
+
+// Sources per staged LDS tile for a history depth: as many as fill a
+// buffer of kHalfRecs records, at most four (one barrier per staged tile).
+inline int pair_staged_tile(int D) { return D <= kHalfRecs ? std::min(4, kHalfRecs / D) : 1; }
+
+namespace {
+
+// sqrt of a positive normal double from the hardware reciprocal square
+// root: one Goldschmidt step and a final Newton correction (about one
+// unit in the last place; no special-value handling, x > 0 here).
+__device__ inline double sqrt_pos(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double sq = x * y;
+    double h = 0.5 * y;
+    double r = __builtin_fma(-sq, h, 0.5);
+    sq = __builtin_fma(sq, r, sq);
+    h = __builtin_fma(h, r, h);
+    r = __builtin_fma(-sq, sq, x);
+    return __builtin_fma(r, h, sq);
+}
+
+// Retarded root, reconstruction and LW field of one pair (Eqs. dt,
+// linear, linear2, LW_E, LW_B).  w1 = {x, y, z, -} is the bracket's older
+// sample, L1 = c (t - t_1); v1 = {v_1, 1/(t_2 - t_1)}, v2 = {v_2, -} the
+// velocity records of the bracket ends.  Writes E and B into f[0..5].
+// Returns false on a numerical failure (negative discriminant, eta <= 0).
+__device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, double L1, double4 v1, double4 v2,
+                               bool before, double kq, double f[6], double &eta_len, double3 &v_ret, bool mid,
+                               double4 w2)
+{
+    const double c = kC_LIGHT;
+    const double c2 = c * c;
+    double dx = rx - w1.x, dy = ry - w1.y, dz = rz - w1.z;
+    // C2 dt^2 + 2 C1h dt + C0 = 0 (Eq. dt with C1 = 2 C1h); the physical
+    // root -(C1h + sqrt(C1h^2 - C2 C0))/C2 in Vieta's form.
+    double C2 = c2 - (v1.x * v1.x + v1.y * v1.y + v1.z * v1.z);
+    double C1h = (dx * v1.x + dy * v1.y + dz * v1.z) - c * L1;
+    double C0 = L1 * L1 - (dx * dx + dy * dy + dz * dz);
+    double disc = C1h * C1h - C2 * C0;
+    bool ok = disc > 0.0;
+    double sq = sqrt_pos(ok ? disc : 1.0);
+    double dtr = C0 * rcp64(sq - C1h);
+    // reconstruction: w = w1 + v1 dt; v = v1 + (v2 - v1) df; a = (v2 - v1)/h
+    double inv_h = before ? 0.0 : v1.w;
+    double gx = v2.x - v1.x, gy = v2.y - v1.y, gz = v2.z - v1.z;
+    double ax = gx * inv_h, ay = gy * inv_h, az = gz * inv_h;  // zero out of history
+    double df = dtr * inv_h;
+    double vrx = v1.x + gx * df, vry = v1.y + gy * df, vrz = v1.z + gz * df;
+    double ex = dx - v1.x * dtr, ey = dy - v1.y * dtr, ez = dz - v1.z * dtr;  // eta
+    // |eta| = c (t - t_r) on the reconstructed segment
+    double en = L1 - c * dtr;
+    if (mid && !before) {
+        // Eq. (mid): the bracket ends' means, eta = r - (w_1 + w_2)/2
+        ex = dx - 0.5 * (w2.x - w1.x);
+        ey = dy - 0.5 * (w2.y - w1.y);
+        ez = dz - 0.5 * (w2.z - w1.z);
+        en = sqrt(ex * ex + ey * ey + ez * ez);
+        vrx = 0.5 * (v1.x + v2.x);
+        vry = 0.5 * (v1.y + v2.y);
+        vrz = 0.5 * (v1.z + v2.z);
+        ok = true;
+    }
+    double ev = c * en - (ex * vrx + ey * vry + ez * vrz);  // eta . v'
+    ok = ok && (en > 0.0) && (ev > 0.0);
+    double inv = rcp64(en * ev);
+    double ien = ev * inv, iev = en * inv;
+    double hx = ex * ien, hy = ey * ien, hz = ez * ien;
+    double px = c * hx - vrx, py = c * hy - vry, pz = c * hz - vrz;  // v'
+    double vv = vrx * vrx + vry * vry + vrz * vrz;
+    // eta x (v' x a)
+    double qx = py * az - pz * ay, qy = pz * ax - px * az, qz = px * ay - py * ax;
+    double rdx = ey * qz - ez * qy, rdy = ez * qx - ex * qz, rdz = ex * qy - ey * qx;
+    double pref = kq * en * (iev * iev * iev);
+    double cv = c2 - vv;
+    double Ex = pref * (cv * px + rdx);
+    double Ey = pref * (cv * py + rdy);
+    double Ez = pref * (cv * pz + rdz);
+    const double ic = 1.0 / c;
+    f[0] = Ex;
+    f[1] = Ey;
+    f[2] = Ez;
+    f[3] = (hy * Ez - hz * Ey) * ic;
+    f[4] = (hz * Ex - hx * Ez) * ic;
+    f[5] = (hx * Ey - hy * Ex) * ic;
+    eta_len = en;
+    v_ret = make_double3(vrx, vry, vrz);
+    return ok;
+}
+
+// Knuth two-sum: s + e == a + b exactly.
+__device__ inline void two_sum(float &s, float &e, float x)
+{
+    float t = s + x;
+    float bb = t - s;
+    float err = (s - (t - bb)) + (x - bb);
+    s = t;
+    e += err;
+}
+
+struct MixedPair {
+    double4 w1, v1, v2;  // FP64 records of the bracket (global memory)
+};
+
+// Root, reconstruction and LW field from FP64 inputs.  The coefficients of
+// the quadratic, the velocity at the root and u = eta - |eta| v/c (which
+// carries the cancellation 1 - eta_hat.beta of nearly forward pairs) are
+// formed in FP64; the root, the normalisations and the LW products in FP32.
+// Since eta = d - v_1 dt and |eta| = L1 - c dt, u = d - (L1/c) v_r +
+// dt (v_r - v_1): the FP64 offset d enters directly and no large terms
+// cancel in FP32.  Writes E, B into f[0..5]; rescued = the FP32 root failed
+// its residual test and was recomputed in FP64.  Returns false on a
+// numerical failure.
+__device__ __forceinline__ bool lw_pair_mixed(double rx, double ry, double rz, double L1d, MixedPair q, bool before,
+                                              float kq, float f[6], bool &rescued)
+{
+    const double c = kC_LIGHT;
+    const double ic = 1.0 / kC_LIGHT;
+    const float cf = (float)kC_LIGHT;
+    // FP64: offset to the bracket sample and the quadratic's coefficients
+    double dxd = rx - q.w1.x, dyd = ry - q.w1.y, dzd = rz - q.w1.z;
+    double C0d = L1d * L1d - (dxd * dxd + dyd * dyd + dzd * dzd);
+    double C2d = c * c - (q.v1.x * q.v1.x + q.v1.y * q.v1.y + q.v1.z * q.v1.z);
+    double C1hd = (dxd * q.v1.x + dyd * q.v1.y + dzd * q.v1.z) - c * L1d;
+    double discd = C1hd * C1hd - C2d * C0d;
+    bool ok = discd > 0.0;
+    // FP32 root in the form without cancellation, checked by its residual
+    float C0 = (float)C0d, C1h = (float)C1hd, C2 = (float)C2d;
+    float sq = __builtin_amdgcn_sqrtf(ok ? (float)discd : 1.0f);
+    float dtr = C1h <= 0.0f ? C0 * __builtin_amdgcn_rcpf(sq - C1h) : -(C1h + sq) * __builtin_amdgcn_rcpf(C2);
+    float res = __builtin_fmaf(__builtin_fmaf(C2, dtr, 2.0f * C1h), dtr, C0);
+    float tol = 8.0f * 5.9604645e-8f * (fabsf(C2) * dtr * dtr + 2.0f * fabsf(C1h * dtr) + fabsf(C0));
+    rescued = !(fabsf(res) <= tol);
+    if (rescued) {
+        double sqd = sqrt(ok ? discd : 0.0);
+        double rd = C1hd <= 0.0 ? C0d / (sqd - C1hd) : -(C1hd + sqd) / C2d;
+        dtr = (float)rd;
+    }
+    // FP64: velocity at the root and u = d - (L1/c) v_r + dt (v_r - v_1)
+    double inv_hd = before ? 0.0 : q.v1.w;
+    double dtd = (double)dtr;
+    double gxd = q.v2.x - q.v1.x, gyd = q.v2.y - q.v1.y, gzd = q.v2.z - q.v1.z;
+    double dfd = dtd * inv_hd;
+    double vrxd = q.v1.x + gxd * dfd, vryd = q.v1.y + gyd * dfd, vrzd = q.v1.z + gzd * dfd;
+    double Lc = L1d * ic, tg = dtd * dfd;
+    double uxd = dxd - Lc * vrxd + tg * gxd, uyd = dyd - Lc * vryd + tg * gyd, uzd = dzd - Lc * vrzd + tg * gzd;
+    // FP32 from here
+    float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+    float vx = (float)q.v1.x, vy = (float)q.v1.y, vz = (float)q.v1.z;
+    float inv_h = (float)inv_hd;
+    float gx = (float)gxd, gy = (float)gyd, gz = (float)gzd;
+    float ax = gx * inv_h, ay = gy * inv_h, az = gz * inv_h;  // zero out of history
+    float df = (float)dfd;
+    float ux = (float)uxd, uy = (float)uyd, uz = (float)uzd;
+    float ex = dx - vx * dtr, ey = dy - vy * dtr, ez = dz - vz * dtr;  // eta
+    float en = (float)L1d - cf * dtr;                                 // |eta| = c (t - t_r)
+    ok = ok && en > 0.0f;
+    float ien = __builtin_amdgcn_rcpf(en);
+    float px = cf * ux * ien, py = cf * uy * ien, pz = cf * uz * ien;  // v' = c eta_hat - v_r
+    float ev = ex * px + ey * py + ez * pz;                           // eta . v' = c |eta| kappa
+    ok = ok && ev > 0.0f;
+    float iev = __builtin_amdgcn_rcpf(ev);
+    float hx = ex * ien, hy = ey * ien, hz = ez * ien;
+    // c^2 - |v_r|^2 from the FP64 value at v_1 plus the small correction
+    float cv = C2 - df * (2.0f * (vx * gx + vy * gy + vz * gz) + df * (gx * gx + gy * gy + gz * gz));
+    float qx = py * az - pz * ay, qy = pz * ax - px * az, qz = px * ay - py * ax;
+    float rdx = ey * qz - ez * qy, rdy = ez * qx - ex * qz, rdz = ex * qy - ey * qx;
+    float pref = kq * en * (iev * iev * iev);
+    float Ex = pref * (cv * px + rdx);
+    float Ey = pref * (cv * py + rdy);
+    float Ez = pref * (cv * pz + rdz);
+    const float icf = (float)ic;
+    f[0] = Ex;
+    f[1] = Ey;
+    f[2] = Ez;
+    f[3] = (hy * Ez - hz * Ey) * icf;
+    f[4] = (hz * Ex - hx * Ez) * icf;
+    f[5] = (hx * Ey - hy * Ex) * icf;
+    return ok;
+}
+
+}  // namespace
+
+template <bool MIX, bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID>
+__device__ __forceinline__ void pair_body(const PairParams &p)
+{
+    extern __shared__ double4 lds[];
+    // LDS address of the dynamic buffer (32-bit, for offset arithmetic)
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)lds;
+    const int D = p.D;
+    const int tid = threadIdx.x;
+    const int nbx = (int)((p.m + kBlockFp64 - 1) / kBlockFp64);
+    int bxi, split;
+    pair_block_coords(nbx, p.nsplit, bxi, split);
+    const int64_t a = (int64_t)bxi * kBlockFp64 + tid;
+    const bool active = a < p.m;
+    const int64_t j0 = (int64_t)split * p.src_per_split;
+    int64_t j1 = j0 + p.src_per_split;
+    if (j1 > p.n_src)
+        j1 = p.n_src;
+
+    double rx = 0, ry = 0, rz = 0;
+    double3 vt = make_double3(0.0, 0.0, 0.0);  // target's present velocity (adaptive step)
+    double eta_min = __longlong_as_double((long long)kPosInfBits), dv2_max = 0.0;
+    int64_t self = -1, tgt = a;  // tgt: index the outputs are written at
+    if (active) {
+        if (p.x) {
+            rx = p.x[a];
+            ry = p.x[p.m + a];
+            rz = p.x[2 * p.m + a];
+            self = p.self_index ? p.self_index[a] : -1;
+        } else {
+            tgt = p.order ? (int64_t)p.order[a] : a;
+            double4 w = p.ring_w[tgt * D + p.head];
+            rx = w.x;
+            ry = w.y;
+            rz = w.z;
+            self = tgt;
+            if (ADAPT) {
+                double4 vn = p.ring_v[tgt * D + p.head];
+                vt = make_double3(vn.x, vn.y, vn.z);
+            }
+        }
+    }
+    static_assert(!MIX || (!ADAPT && !MID && GUESS <= 2), "mixed precision: fixed step, no warm start");
+    // field sums: FP64 with Neumaier compensation, or FP32 with two-sum
+    using Real = std::conditional_t<MIX, float, double>;
+    Real sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
+    Real acc[6] = {0, 0, 0, 0, 0, 0};
+    constexpr int kPlainRun = MIX ? 4 : 16;  // sources per plain partial
+    const float kqf = (float)p.kq;
+    int groups_in_acc = 0;
+    int probes = 0, nbefore = 0, npairs = 0, nfall = 0, nresc = 0;
+    // first (lowest) source of a failing pair; sources number below 2^31
+    int32_t fail_j = INT32_MAX;
+    const float inv_cdt = (float)(1.0 / (kC_LIGHT * p.dt));
+
+    // LDS: nbuf tile buffers, then the light distance of every logical slot
+    // (shared by all sources).  A buffer holds its TS * D records as two
+    // arrays of 16-byte halves, {x, y} then {z, L^2}, hrec halves apart:
+    // lanes that probe different slots then spread over twice as many LDS
+    // bank groups as with 32-byte records.  With two buffers the distance is
+    // the fixed kHalfRecs, so a probe's two reads share one address (the
+    // second one at an immediate offset).
+    const int nbuf = p.nbuf;
+    // A staged tile holds G groups of S sources; the S sources of a group
+    // are searched in lockstep, and one barrier per staged tile serves all
+    // its groups.
+    const int G = p.groups;
+    const int TS = S * G;
+    const int hrec = nbuf == 2 ? kHalfRecs : TS * D;
+    double2 *const halves = reinterpret_cast<double2 *>(lds);
+    double *Ls = reinterpret_cast<double *>(halves + nbuf * 2 * hrec);
+    struct TileView {
+        const double2 *xy, *zl;
+        __device__ double4 rec(int i) const
+        {
+            const double2 a = xy[i], b = zl[i];
+            return make_double4(a.x, a.y, b.x, b.y);
+        }
+    };
+    auto view = [&](int bi, int g) {
+        const double2 *base = halves + bi * 2 * hrec + g * S * D;
+        return TileView{base, base + hrec};
+    };
+    // the present time is the newest slot's (the clock lives in T)
+    const double tnow = p.T[p.head];
+    for (int b = tid; b < D; b += kBlockFp64) {
+        int ph = p.head - b;
+        ph += ph < 0 ? D : 0;
+        Ls[b] = kC_LIGHT * (tnow - p.T[ph]);
+    }
+    // Tile records are prefetched into registers one tile ahead (the first
+    // two records of each thread), so their HBM/L2 latency overlaps the
+    // previous tile's work; deeper histories load the rest in place.
+    // Record q of a tile: source q / D (q < TS D, TS <= 4), slot q % D.
+    auto src_of = [&](int q) { return (q >= D) + (q >= 2 * D) + (q >= 3 * D); };
+    auto fetch = [&](int64_t jt, int ns, int q) -> double4 {
+        int s = src_of(q);
+        int b = q - s * D;
+        double4 w = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (b < D && s < ns) {
+            int ph = p.head - b;
+            ph += ph < 0 ? D : 0;
+            w = p.ring_w[(jt + s) * D + ph];
+        }
+        return w;
+    };
+    auto put = [&](int bi, int ns, int q, double4 w) {
+        int s = src_of(q);
+        int b = q - s * D;
+        if (b < D && s < ns) {
+            double L = Ls[b];
+            double2 *xy = halves + bi * 2 * hrec + s * D + b;
+            xy[0] = make_double2(w.x, w.y);
+            xy[hrec] = make_double2(w.z, L * L);
+        }
+    };
+    auto stage = [&](int bi, int64_t jt, int ns, double4 r0, double4 r1) {
+        put(bi, ns, tid, r0);
+        put(bi, ns, tid + kBlockFp64, r1);
+        for (int q = tid + 2 * kBlockFp64; q < ns * D; q += kBlockFp64) {
+            int s = q / D, b = q - (q / D) * D;
+            int ph = p.head - b;
+            ph += ph < 0 ? D : 0;
+            put(bi, ns, q, p.ring_w[(jt + s) * D + ph]);
+        }
+    };
+    auto tile_size = [&](int64_t jt) { return (int)((j1 - jt) < TS ? (j1 - jt) : TS); };
+    double4 pf0 = make_double4(0.0, 0.0, 0.0, 0.0), pf1 = pf0;
+    if (j0 < j1) {
+        pf0 = fetch(j0, tile_size(j0), tid);
+        pf1 = fetch(j0, tile_size(j0), tid + kBlockFp64);
+    }
+    // Two buffers: tile i + 1 is written while tile i is searched, and one
+    // barrier per tile both publishes tile i + 1 and retires tile i's
+    // buffer for tile i + 2.  One buffer (deep histories): stage, then
+    // search, with a barrier on either side.
+    if (nbuf == 2 && j0 < j1) {
+        __syncthreads();
+        stage(0, j0, tile_size(j0), pf0, pf1);
+        if (j0 + TS < j1) {
+            pf0 = fetch(j0 + TS, tile_size(j0 + TS), tid);
+            pf1 = fetch(j0 + TS, tile_size(j0 + TS), tid + kBlockFp64);
+        }
+        __syncthreads();
+    }
+    // previous-step brackets of the next tile's sources (warm start)
+    uint16_t knext[S], kcur[S];
+    auto load_brackets = [&](int64_t jt) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            knext[s] = active && jt + s < j1 ? p.kc[(jt + s) * p.m + a] : kBracketBefore;
+    };
+    if (GUESS == 4 && j0 < j1)
+        load_brackets(j0);
+    int it = 0;
+    for (int64_t jts = j0; jts < j1; jts += TS, ++it) {
+        const int cb = nbuf == 2 ? (it & 1) : 0;
+        if (nbuf == 2) {
+            if (jts + TS < j1) {
+                stage(cb ^ 1, jts + TS, tile_size(jts + TS), pf0, pf1);
+                if (jts + 2 * TS < j1) {
+                    pf0 = fetch(jts + 2 * TS, tile_size(jts + 2 * TS), tid);
+                    pf1 = fetch(jts + 2 * TS, tile_size(jts + 2 * TS), tid + kBlockFp64);
+                }
+            }
+        } else {
+            __syncthreads();
+            stage(0, jts, tile_size(jts), pf0, pf1);
+            __syncthreads();
+            if (jts + TS < j1) {
+                pf0 = fetch(jts + TS, tile_size(jts + TS), tid);
+                pf1 = fetch(jts + TS, tile_size(jts + TS), tid + kBlockFp64);
+            }
+        }
+      for (int grp = 0; grp < G && jts + grp * S < j1; ++grp) {
+        const int64_t jt = jts + grp * S;
+        const int ns = (int)((j1 - jt) < S ? (j1 - jt) : S);
+        if (GUESS == 4) {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                kcur[s] = knext[s];
+            if (jt + S < j1)
+                load_brackets(jt + S);
+        }
+        const TileView cur = view(cb, grp);
+        if (active) {
+            bool valid[S];
+            int64_t jj[S];
+            int bk[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                jj[s] = jt + (s < ns ? s : 0);
+                valid[s] = s < ns && jj[s] != self;
+                if (KSTAR && s < ns && jj[s] == self)
+                    p.kstar[a * p.n_src + jj[s]] = 0;
+                // a target on the source's present position: eta = 0
+                double4 wn = cur.rec(s * D);
+                if (valid[s] && rx == wn.x && ry == wn.y && rz == wn.z) {
+                    fail_j = min(fail_j, (int32_t)jj[s]);
+                    valid[s] = false;
+                }
+            }
+
+            // bracket velocity records (they carry 1/(t_2 - t_1)), root,
+            // reconstruction, LW field and accumulation of tile source s
+            auto load_v = [&](int s, int b, double4 &v1, double4 &v2) {
+                const int bb = b < 0 ? D - 1 : b;
+                int ph1 = p.head - bb;
+                ph1 += ph1 < 0 ? D : 0;
+                int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
+                // uniform row base plus 32-bit lane offsets
+                const char *row = reinterpret_cast<const char *>(p.ring_v + jj[s] * D);
+                v1 = *reinterpret_cast<const double4 *>(row + (uint32_t)ph1 * (uint32_t)sizeof(double4));
+                // unused (inv_h = 0) out of history
+                v2 = *reinterpret_cast<const double4 *>(row + (uint32_t)ph2 * (uint32_t)sizeof(double4));
+            };
+            auto finish = [&](int s, int b, double4 v1, double4 v2) {
+                const bool before = b < 0;
+                const int bb = before ? D - 1 : b;
+                Real f[6];
+                double en = 0.0;
+                double3 vr = make_double3(0.0, 0.0, 0.0);
+                bool ok;
+                if constexpr (MIX) {
+                    bool resc = false;
+                    ok = lw_pair_mixed(rx, ry, rz, Ls[bb], MixedPair{cur.rec(s * D + bb), v1, v2}, before, kqf, f,
+                                       resc);
+                    if (COUNT && valid[s])
+                        nresc += resc ? 1 : 0;
+                } else {
+                    ok = lw_pair(rx, ry, rz, cur.rec(s * D + bb), Ls[bb], v1, v2, before, p.kq, f, en, vr, MID,
+                                 MID ? cur.rec(s * D + (bb > 0 ? bb - 1 : 0)) : make_double4(0.0, 0.0, 0.0, 0.0));
+                }
+                if (valid[s]) {
+                    if (ok) {
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            acc[k] += f[k];
+                        if (ADAPT && en >= p.eta_allow) {
+                            const double dx = vt.x - vr.x, dy = vt.y - vr.y, dz = vt.z - vr.z;
+                            eta_min = fmin(eta_min, en);
+                            dv2_max = fmax(dv2_max, dx * dx + dy * dy + dz * dz);
+                        }
+                    } else {
+                        fail_j = min(fail_j, (int32_t)jj[s]);
+                    }
+                    if (KSTAR)
+                        p.kstar[a * p.n_src + jj[s]] = before ? -1 : b;
+                    if (COUNT) {
+                        npairs += 1;
+                        nbefore += before ? 1 : 0;
+                    }
+                }
+            };
+
+            if (GUESS == 0 || GUESS >= 4) {
+                if (GUESS != 4) {
+                    // The paper's search: oldest sample first, then bisection
+                    // of the whole history; a fixed number of halvings keeps
+                    // the S searches in lockstep (extra halvings of a one-step
+                    // bracket change nothing).
+                    bool inside[S];
+                    // LDS byte address of the record of xb: f(xb) <= 0, the
+                    // bracket lies in (xb, xb + n]
+                    uint32_t xo[S];
+                    // LDS byte address of the group's first {x, y} half
+                    const uint32_t xy0 =
+                        lds_base + (uint32_t)(cb * 2 * hrec + grp * S * D) * (uint32_t)sizeof(double2);
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        inside[s] = lightcone_positive(cur.rec(s * D + D - 1), rx, ry, rz);
+                        xo[s] = xy0 + (uint32_t)(s * D) * (uint32_t)sizeof(double2);
+                    }
+                    bool any = false;
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        any = any || (inside[s] && valid[s]);
+                    // halving widths depend on D only: uniform across lanes
+                    auto halve = [&](auto zl_off) {
+                        for (int n = D - 1; n > 1;) {
+                            const int half = n >> 1;
+                            const uint32_t hb = (uint32_t)half * (uint32_t)sizeof(double2);
+#pragma unroll
+                            for (int s = 0; s < S; ++s) {
+                                const uint32_t mo = xo[s] + hb;
+                                typedef double dv2 __attribute__((ext_vector_type(2)));
+                                const dv2 va = *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)mo;
+                                const dv2 vb =
+                                    *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)(mo + (uint32_t)zl_off);
+                                const double4 rec = make_double4(va.x, va.y, vb.x, vb.y);
+                                xo[s] = lightcone_positive(rec, rx, ry, rz) ? xo[s] : mo;
+                            }
+                            n -= half;
+                        }
+                    };
+                    if (__any(any)) {
+                        if (nbuf == 2)
+                            halve(std::integral_constant<uint32_t, kHalfRecs * sizeof(double2)>{});
+                        else
+                            halve((uint32_t)hrec * (uint32_t)sizeof(double2));
+                    }
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        bk[s] = inside[s] ? (int)((xo[s] - xy0) / (uint32_t)sizeof(double2)) - s * D + 1 : -1;
+                        if (COUNT && valid[s])
+                            probes += inside[s] ? 1 + p.nit : 1;
+                    }
+                } else {
+                    // Warm start from the previous step's bracket (back
+                    // offsets are relative to the newest slot, so a pair
+                    // whose geometry is unchanged keeps its value): confirm
+                    // it with the two samples that define it, issued
+                    // together for the S sources; a pair whose bracket moved
+                    // gallops from the old one.
+                    bool hit[S];
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        const int g = kcur[s];
+                        const bool was_before = g == kBracketBefore;
+                        const bool in_range = g >= 1 && g < D;
+                        const int ga = in_range ? g : D - 1;  // 1 <= ga <= D - 1
+                        const bool fa = lightcone_positive(cur.rec(s * D + ga), rx, ry, rz);
+                        const bool fb = lightcone_positive(cur.rec(s * D + ga - 1), rx, ry, rz);
+                        hit[s] = was_before ? !fa : (in_range && fa && !fb);
+                        // a bracket index leaves this block only if it is
+                        // one (the entry of an excluded pair is never
+                        // written and may hold anything)
+                        bk[s] = in_range ? g : -1;
+                        if (COUNT && valid[s])
+                            probes += was_before || g == 1 ? 1 : 2;
+                    }
+                    for (int s = 0; s < S; ++s) {
+                        if (!hit[s] && valid[s]) {
+                            auto test = [&](int bb) { return lightcone_positive(cur.rec(s * D + bb), rx, ry, rz); };
+                            const int g = kcur[s];
+                            int fb = 0;
+                            bk[s] = search_guided(test, D, g == kBracketBefore || g >= D ? (float)(D - 1) : (float)g, 6,
+                                                  probes, fb);
+                            nfall += fb;
+                        }
+                    }
+                }
+                if (GUESS >= 4) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        if (valid[s])
+                            p.kc[jj[s] * p.m + a] = bk[s] < 0 ? kBracketBefore : (uint16_t)bk[s];
+                }
+                double4 v1[S], v2[S];
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    load_v(s, bk[s], v1[s], v2[s]);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    finish(s, bk[s], v1[s], v2[s]);
+            } else {
+                // guided searches, one source at a time
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    int b = -1;
+                    if (valid[s]) {
+                        auto test = [&](int bb) { return lightcone_positive(cur.rec(s * D + bb), rx, ry, rz); };
+                        double4 wn = cur.rec(s * D);
+                        float g;
+                        if (GUESS == 2) {
+                            double4 vn = p.ring_v[jj[s] * D + p.head];
+                            g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
+                        } else if (p.g_ratio) {
+                            // surrogate, one evaluation per group: the group's
+                            // correction factor to straight-line motion times
+                            // this target's straight-line look-back
+                            double4 vn = p.ring_v[jj[s] * D + p.head];
+                            float gh = p.G[jj[s] * p.g_groups + (a >> p.g_shift)];
+                            g = gh * ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
+                        } else {
+                            // surrogate per pair: predicted c (t - t_r) / |r - w_n| times the distance
+                            float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
+                            float gh = p.G[jj[s] * p.g_groups + (a >> p.g_shift)];
+                            g = gh * __builtin_amdgcn_sqrtf(Rx * Rx + Ry * Ry + Rz * Rz) * inv_cdt;
+                        }
+                        int fb = 0;
+                        b = search_guided(test, D, g, 6, probes, fb);
+                        nfall += fb;
+                    }
+                    double4 v1, v2;
+                    load_v(s, b, v1, v2);
+                    finish(s, b, v1, v2);
+                }
+            }
+        }
+        // plain partial sums over kPlainRun sources, then one compensated
+        // merge (the same cadence for every search mode: results are
+        // bit-identical)
+        if (++groups_in_acc * S == kPlainRun) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                if constexpr (MIX)
+                    two_sum(sum[k], comp[k], acc[k]);
+                else
+                    neumaier(sum[k], comp[k], acc[k]);
+                acc[k] = 0;
+            }
+            groups_in_acc = 0;
+        }
+      }
+        if (nbuf == 2)
+            __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if constexpr (MIX)
+            two_sum(sum[k], comp[k], acc[k]);
+        else
+            neumaier(sum[k], comp[k], acc[k]);
+    }
+    if (active) {
+        double *out = p.part + (int64_t)split * 12 * p.m + tgt;
+        for (int k = 0; k < 6; ++k) {
+            out[k * p.m] = (double)sum[k];
+            out[(6 + k) * p.m] = (double)comp[k];
+        }
+        if (fail_j != INT32_MAX)
+            report_error(p.err, tgt, fail_j, kErrCoincident);
+    }
+    if (ADAPT) {
+        // one atomic pair per wavefront
+        for (int off = 32; off > 0; off >>= 1) {
+            eta_min = fmin(eta_min, __shfl_xor(eta_min, off));
+            dv2_max = fmax(dv2_max, __shfl_xor(dv2_max, off));
+        }
+        if ((tid & 63) == 0) {
+            atomicMin(&p.ad[0], (unsigned long long)__double_as_longlong(eta_min));
+            atomicMax(&p.ad[1], (unsigned long long)__double_as_longlong(dv2_max));
+        }
+    }
+    if (COUNT) {
+        // one atomic per wavefront
+        unsigned long long c0 = npairs, c1 = nbefore, c2 = probes, c3 = nfall, c4 = nresc;
+        for (int off = 32; off > 0; off >>= 1) {
+            c0 += __shfl_down(c0, off);
+            c1 += __shfl_down(c1, off);
+            c2 += __shfl_down(c2, off);
+            c3 += __shfl_down(c3, off);
+            c4 += __shfl_down(c4, off);
+        }
+        if ((tid & 63) == 0) {
+            atomicAdd(&p.counters[0], c0);
+            atomicAdd(&p.counters[1], c1);
+            atomicAdd(&p.counters[2], c2);
+            atomicAdd(&p.counters[4], c3);
+            if (MIX)
+                atomicAdd(&p.counters[3], c4);
+        }
+    }
+}
+
+}  // namespace empp
