@@ -222,17 +222,18 @@ empp_status empp_get_timing(empp_ctx *ctx, empp_timing *out);
 
 /* ---- surrogate network (retarded-delay guess) ----------------------------
  * A 10 -> 128 -> 128 -> 1 SiLU network with BF16 weights on the matrix
- * cores (FP32 accumulation) predicts z = log(c (t - t_r) / |r - w_n|) of a
- * (target, source) pair from 10 features: (r - w_n)/sigma_ref (3), the
- * source's newest velocity / c (3), its displacement over the last 4 steps
- * / (c (T_n - T_{n-4})) (3) and log1p((t - T_n)/dt) (1).  With guess mode
- * EMPP_GUESS_MLP it is evaluated once per (group of 64 consecutive targets
- * -- in the spatial order when stepping --, source) at the group centroid;
- * its ratio to the straight-line value there (a source coasting with its
- * newest velocity) scales each target's own straight-line look-back.  The
- * exact search then finishes every bracket, so the network changes cost,
- * never results.  Not part of the paper's
- * method.  Parameters: the flat vector W1[128][10], b1[128], W2[128][128],
+ * cores (FP32 accumulation) corrects the straight-line retarded delay of a
+ * (target, source) pair: the model's delay is s_line exp(z), s_line the
+ * look-back c (t - t_r) of a source coasting with its newest velocity, and
+ * the network output z is trained on log(c (t - t_r) / s_line).  Its 10
+ * features: (r - w_n)/sigma_ref (3), the source's newest velocity / c (3),
+ * its displacement over the last 4 steps / (c (T_n - T_{n-4})) (3) and
+ * log1p((t - T_n)/dt) (1).  With guess mode EMPP_GUESS_MLP it is evaluated
+ * once per (group of 64 consecutive targets -- in the spatial order when
+ * stepping --, source) at the group centroid, and exp(z) there scales each
+ * target's own straight-line look-back.  The exact search then finishes
+ * every bracket, so the network changes cost, never results.  Not part of
+ * the paper's method.  Parameters: the flat vector W1[128][10], b1[128], W2[128][128],
  * b2[128], W3[128], b3 (18049 floats, FP32 masters).                     */
 typedef struct {
     int64_t steps;         /* optimizer steps                                */

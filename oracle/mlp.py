@@ -1,15 +1,16 @@
 """FP64 oracle of the retarded-delay surrogate network -- TEST INFRASTRUCTURE ONLY.
 
-The network maps 10 pair features to the normalised retarded delay
-g = c (t - t_r) / |r - w_n| of a (target, source) pair:
+The model predicts the retarded look-back s = c (t - t_r) of a (target,
+source) pair from 10 pair features as s_line exp(z), where s_line is the
+look-back to a source coasting with its newest velocity (a closed form of
+the features, straight_line_lookback) and z the network output:
 
     h1 = silu(W1 x + b1)     W1: 128 x 10
     h2 = silu(W2 h1 + b2)    W2: 128 x 128
     z  = W3 h2 + b3          W3: 1 x 128
-    g_hat = exp(z)
 
-It is trained on z against log g (mean squared error), i.e. on the
-relative error of the delay.  Weights and inputs are rounded to bfloat16
+It is trained on z against log(s / s_line) (mean squared error), i.e. on
+the relative error of the delay; z = 0 is the straight-line guess.  Weights and inputs are rounded to bfloat16
 (round to nearest even) before use, as the GPU kernels store them; all
 arithmetic here is float64.
 
@@ -117,6 +118,20 @@ def features(y_i, w_n, v_n, w_n4, T_n, T_n4, t, dt, sigma_ref):
     slope = (w_n - w_n4) / (C_LIGHT * (T_n - T_n4))
     lg = np.full((1, rel.shape[1]), np.log1p((t - T_n) / dt))
     return np.concatenate([rel, beta, slope, lg]).T
+
+
+def straight_line_lookback(y_i, w_n, v_n):
+    """Light distance s = c (t - t_r) from y_i back to a source that moved
+    with constant velocity v_n and is at w_n at the present time t: with
+    R = y_i - w_n and beta = v_n / c the source was at w_n - beta s, so
+    |R + beta s| = s, i.e. (1 - beta^2) s^2 - 2 (R . beta) s - |R|^2 = 0;
+    the positive root.  Arrays [3, P]; returns [P]."""
+    R = y_i - w_n
+    beta = v_n / C_LIGHT
+    rb = np.sum(R * beta, axis=0)
+    R2 = np.sum(R * R, axis=0)
+    g2 = 1.0 - np.sum(beta * beta, axis=0)
+    return (rb + np.sqrt(rb * rb + g2 * R2)) / g2
 
 
 def normalised_delay(y_i, w_n, t, tr):

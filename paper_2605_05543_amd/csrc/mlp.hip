@@ -4,10 +4,13 @@
 // (forward + backward + Adam) and the sampling of training pairs from the
 // stored histories.
 //
-// The network maps features of a (target, source) pair to z = log g with
-// g = c (t - t_r) / |r - w_n|, the retarded look-back in units of the
-// present separation; a guided search starts from it.  It never decides
-// a result: the exact search finishes every bracket.
+// The model predicts the normalised retarded delay g = c (t - t_r) /
+// |r - w_n| of a (target, source) pair as g_line exp(z): g_line is the
+// value for a source coasting with its newest velocity (a closed form of
+// the features) and the network output z corrects it, so an untrained
+// network (z = 0) reproduces the straight-line guess.  A guided search
+// starts from the prediction; it never decides a result: the exact search
+// finishes every bracket.
 //
 // Layout of the flat parameter vector (FP32 masters, 18049 values):
 //   W1[128][10], b1[128], W2[128][128], b2[128], W3[1][128], b3[1].
@@ -485,7 +488,8 @@ __global__ void mlp_pack_kernel(const float *master, MlpPacked *net)
 // ---------------------------------------------------------------------------
 // Pair features and exact targets from the stored histories.
 //   features: (r - w_n)/sigma_ref, v_n/c, (w_n - w_{n-4})/(c (T_n - T_{n-4})),
-//             log1p((t - T_n)/dt);  target: log(c (t - t_r) / |r - w_n|).
+//             log1p((t - T_n)/dt);  target: log(c (t - t_r) / s_line), s_line
+//             the look-back of a source coasting with its newest velocity.
 // Pairs are given (target particle, source) or drawn with a counter-based
 // generator (splitmix64 of seed + pair counter).
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
@@ -544,7 +548,13 @@ __device__ void pair_features(const SampleParams &p, int64_t i, int64_t j, float
     double sq = sqrt(fmax(C1h * C1h - C2 * C0, 0.0));
     double dtr = C1h <= 0.0 ? C0 / (sq - C1h) : -(C1h + sq) / C2;
     double look = L1 - c * dtr;  // c (t - t_r)
-    yrow[0] = (float)log(look / sqrt(Rx * Rx + Ry * Ry + Rz * Rz));
+    // the model's fixed term: the look-back of a source coasting with its
+    // newest velocity, s solving (1 - beta^2) s^2 - 2 (R.beta) s - R^2 = 0
+    double bx = vn.x / c, by = vn.y / c, bz = vn.z / c;
+    double rb = Rx * bx + Ry * by + Rz * bz, R2 = Rx * Rx + Ry * Ry + Rz * Rz;
+    double g2 = 1.0 - (bx * bx + by * by + bz * bz);
+    double s_line = (rb + sqrt(rb * rb + g2 * R2)) / g2;
+    yrow[0] = (float)log(look / s_line);
 }
 
 __global__ void mlp_sample_kernel(SampleParams p, const int64_t *tgt, const int64_t *src, int64_t count, float *X,
@@ -592,7 +602,7 @@ __global__ __launch_bounds__(256) void mlp_group_guess_kernel(const MlpPacked *n
     for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * 16 * kTiles; base < rows;
          base += (int64_t)gridDim.x * 64 * kTiles) {
         s4 xb[kTiles];
-        float gb[kTiles];  // straight-line delay ratio at the centroid (ratio mode)
+        float gb[kTiles];  // straight-line normalised delay s_line / |R| (per-pair mode)
 #pragma unroll
         for (int t = 0; t < kTiles; ++t) {
             const int64_t row = base + t * 16 + (l & 15);
@@ -619,9 +629,8 @@ __global__ __launch_bounds__(256) void mlp_group_guess_kernel(const MlpPacked *n
             }
             xb[t] = feature_operand(f);
             gb[t] = 1.0f;
-            if (p.ratio) {
-                // straight-line look-back from the centroid in units of
-                // |centroid - w_n|
+            if (!p.ratio) {
+                // straight-line look-back in units of |r - w_n|
                 const float Rx = f[0] * sig, Ry = f[1] * sig, Rz = f[2] * sig;
                 const float R2 = Rx * Rx + Ry * Ry + Rz * Rz;
                 const float rb = Rx * f[3] + Ry * f[4] + Rz * f[5];
@@ -637,9 +646,12 @@ __global__ __launch_bounds__(256) void mlp_group_guess_kernel(const MlpPacked *n
         for (int t = 0; t < kTiles; ++t) {
             const int64_t row = base + t * 16 + (l & 15);
             if (l < 16 && row < rows) {
+                // the network corrects the straight-line delay by exp(z):
+                // ratio mode stores the correction, per-pair mode the
+                // normalised delay
                 float g = __expf(zz[t]);
-                if (p.ratio)
-                    g = gb[t] > 0.0f ? g / gb[t] : 1.0f;
+                if (!p.ratio)
+                    g *= gb[t];
                 G[row] = g;
             }
         }

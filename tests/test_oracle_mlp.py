@@ -88,3 +88,36 @@ def test_adam_matches_torch():
         opt.step()
         cur, m, v = mlp.adam_step(cur, m, v, grad, step, 1e-3)
     assert np.max(np.abs(cur - pt.detach().numpy())) < 1e-14
+
+
+def test_straight_line_lookback_closed_forms():
+    """A source at rest: the look-back is the distance.  A source heading
+    straight at the target at speed beta c: d / (1 - beta).  Receding:
+    d / (1 + beta).  Moving across the line of sight: d / sqrt(1 - beta^2)."""
+    C = mlp.C_LIGHT
+    d, beta = 2.5e-3, 0.94
+    y = np.array([[d, d, d, 0.0], [0.0, 0.0, 0.0, d], [0.0, 0.0, 0.0, 0.0]])
+    w = np.zeros((3, 4))
+    v = np.array([[0.0, beta * C, -beta * C, beta * C], [0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 0.0]])
+    s = mlp.straight_line_lookback(y, w, v)
+    want = np.array([d, d / (1 - beta), d / (1 + beta), d / np.sqrt(1 - beta * beta)])
+    assert np.allclose(s, want, rtol=1e-14, atol=0)
+
+
+def test_straight_line_lookback_matches_retarded_solve():
+    """On histories of uniform motion the exact retarded solve of the
+    oracle (bracket and segment root inside the history, straight
+    extrapolation before it) lands on the straight-line look-back."""
+    import oracle
+    from paper_2605_05543_amd import bunch
+
+    n, D, dt = 24, 64, 1e-13
+    T, w, v = bunch.wiggly_history(n, D, dt, beta=0.9, accel_rel=0.0, seed=4)
+    rng = np.random.default_rng(5)
+    x = 1.5e-3 * rng.standard_normal((3, 40))
+    ret = oracle.get().retarded(T, w, v, T[-1], x)
+    look = mlp.C_LIGHT * (T[-1] - ret["tr"])  # [40, n]
+    assert 0.05 < (ret["kstar"] >= 0).mean() < 0.95  # both cases present
+    for j in range(n):
+        s = mlp.straight_line_lookback(x, w[-1][:, j:j + 1], v[-1][:, j:j + 1])
+        assert np.allclose(look[:, j], s, rtol=1e-11, atol=0)
