@@ -89,7 +89,7 @@ def train_surrogate(ctx, wl, r, epochs=2):
     return rep
 
 
-def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2):
+def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_log2=0):
     import torch
 
     from paper_2605_05543_amd._lib import Context
@@ -97,7 +97,7 @@ def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2):
     n = wl.bunch.n
     ctx = Context(n=n, depth=wl.depth, q=-bunch.E_CHARGE, m=bunch.M_ELECTRON, dt=wl.dt, ext_field=wl.ext_field,
                   dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re, precision=precision,
-                  guess=4 if guess == 4 else 0)
+                  guess=4 if guess == 4 else 0, guess_group_log2=group_log2)
     ctx.init_bunch(r, u, 0.0)
     ctx.init_history_straight()
     train_rep = train_surrogate(ctx, wl, r, train_epochs) if guess == 1 else None
@@ -136,6 +136,8 @@ def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2):
         "guess_kernel_ms": tim["guess_ms"] / max(1, tim["guess_launches"]) if tim["guess_launches"] else 0.0,
         "rescues_per_pair": cnt["rescues"] / cnt["pairs"],
     }
+    if guess == 1:
+        out["targets_per_guess"] = 1 << (group_log2 or 6)
     if train_rep:
         out["surrogate_training"] = train_rep
     log(f"  {out['precision']}/{out['guess']}: {out['pair_evals_per_s']:.3e} pair-evals/s, "
@@ -175,8 +177,9 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-epochs", type=int, default=2, help="passes over the surrogate's training pairs")
-    ap.add_argument("--paths", default="fp64:bisect,mixed:mlp,mixed:bisect,mixed:ballistic,fp64:ballistic,"
-                                        "fp64:previous")
+    ap.add_argument("--paths", default="fp64:bisect,mixed:mlp/12,mixed:mlp,mixed:bisect,mixed:ballistic,"
+                                        "fp64:ballistic,fp64:previous",
+                    help="precision:search[/k], k = log2 of the targets per surrogate evaluation")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -205,7 +208,9 @@ def main():
     results = []
     for spec in args.paths.split(","):
         p, g = spec.split(":")
-        results.append(run_path(wl, r, u, pmap[p], gmap[g], args.steps, args.warmup, args.train_epochs))
+        g, _, k = g.partition("/")
+        results.append(run_path(wl, r, u, pmap[p], gmap[g], args.steps, args.warmup, args.train_epochs,
+                                int(k or 0)))
     plain = results[0]
     # headline: the mixed-precision surrogate-guided path when it was run,
     # else the first mixed path, else the plain FP64 path

@@ -118,6 +118,11 @@ typedef struct {
      * Sec. 2.2 (Eq. linear, the method); 1 = the earlier midpoint values of
      * Eq. (mid), an accuracy ablation (FP64 path, bisection, fixed step).  */
     int32_t recon;
+    /* Targets per surrogate evaluation in guess mode EMPP_GUESS_MLP:
+     * 2^guess_group_log2 consecutive targets (in the spatial order when
+     * stepping) share one network evaluation at their centroid; 6 to 16,
+     * 0 means 6 (64 targets, one wavefront).                              */
+    int32_t guess_group_log2;
 } empp_config;
 
 typedef struct {

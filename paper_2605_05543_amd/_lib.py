@@ -49,7 +49,7 @@ class Config(ctypes.Structure):
         ("source_splits", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_uint64), ("adaptive", ctypes.c_int32), ("c_dt", ctypes.c_double),
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double), ("eta_allow", ctypes.c_double),
-        ("recon", ctypes.c_int32),
+        ("recon", ctypes.c_int32), ("guess_group_log2", ctypes.c_int32),
     ]
 
 
@@ -348,13 +348,14 @@ class Context:
 
     def __init__(self, *, n, depth, q, m, dt, ext_field=0, dipole_b0=0.0, dipole_re=0.0,
                  precision=EMPP_FP64, guess=EMPP_GUESS_BISECT, device=0, source_splits=0, use_torch=True,
-                 adaptive=False, c_dt=0.05, dt_min=1e-15, dt_max=1e-12, eta_allow=0.0, recon=0):
+                 adaptive=False, c_dt=0.05, dt_min=1e-15, dt_max=1e-12, eta_allow=0.0, recon=0,
+                 guess_group_log2=0):
         self.n, self.depth = int(n), int(depth)
         cfg = Config(n=self.n, depth=self.depth, ext_field=int(ext_field), q=float(q), m=float(m), dt=float(dt),
                      dipole_b0=float(dipole_b0), dipole_re=float(dipole_re), precision=int(precision),
                      guess=int(guess), device=int(device), source_splits=int(source_splits),
                      adaptive=int(bool(adaptive)), c_dt=float(c_dt), dt_min=float(dt_min), dt_max=float(dt_max),
-                     eta_allow=float(eta_allow), recon=int(recon))
+                     eta_allow=float(eta_allow), recon=int(recon), guess_group_log2=int(guess_group_log2))
         self._ws = None
         self.stream_handle = None
         if use_torch:

@@ -49,6 +49,7 @@ hipError_t launch_mlp_group_guess(const MlpPacked *net, const GuessParams &p, fl
 hipError_t launch_group_centroid(const double4 *ring_w, const int32_t *order, int64_t N, int D, int head,
                                  double3 *centroid, hipStream_t s);
 hipError_t launch_group_centroid_x(const double *x, int64_t m, int group, double3 *centroid, hipStream_t s);
+hipError_t launch_merge_centroids(const double3 *cent64, int64_t m, int ratio, double3 *out, hipStream_t s);
 }  // namespace empp
 
 using namespace empp;
@@ -218,6 +219,8 @@ empp_status validate(const empp_config *c)
         return fail(EMPP_EUNSUPPORTED, "warm-start brackets are implemented for the FP64 path");
     if (c->recon != 0 && c->recon != 1)
         return fail(EMPP_EINVAL, "recon must be 0 (linear) or 1 (midpoint)");
+    if (c->guess_group_log2 != 0 && (c->guess_group_log2 < 6 || c->guess_group_log2 > 16))
+        return fail(EMPP_EINVAL, "guess_group_log2 must be 0 or 6..16");
     if (c->recon == 1 && (c->precision != EMPP_FP64 || c->guess != EMPP_GUESS_BISECT || c->adaptive))
         return fail(EMPP_EUNSUPPORTED, "the midpoint ablation runs on the FP64 path with bisection and a fixed step");
     if (c->adaptive) {
@@ -270,7 +273,7 @@ struct empp_ctx {
         float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *part = nullptr;
         MlpPacked *net = nullptr;
         float *G = nullptr;
-        double3 *cent = nullptr;
+        double3 *cent = nullptr, *cent_big = nullptr;
         int part_blocks = 512;
         int64_t adam_step = 0;
         double sigma_ref = 0.0;
@@ -366,7 +369,7 @@ PairParams pair_params(empp_ctx *ctx)
     p.part = ctx->part();
     p.err = ctx->err();
     p.counters = ctx->counters();
-    p.guess = ctx->cfg.guess == EMPP_GUESS_MLP_PAIR ? EMPP_GUESS_MLP : ctx->cfg.guess;
+    p.guess = ctx->cfg.guess;
     // the bracket cache serves the step's launch only
     if (p.guess == EMPP_GUESS_PREVIOUS)
         p.guess = EMPP_GUESS_BISECT;
@@ -436,33 +439,40 @@ hipError_t launch_guesses(empp_ctx *ctx, PairParams &p, float *G_pair = nullptr,
             p.G = G_pair;
             p.g_groups = p.m;
             p.g_shift = 0;
-            p.g_ratio = 0;
             return launch_mlp_group_guess(ctx->sg.net, gp, G_pair, ctx->stream);
         });
     }
     if (ctx->cfg.guess != EMPP_GUESS_MLP)
         return hipSuccess;
     return timed(ctx, 2, [&]() {
-        hipError_t e = p.x ? launch_group_centroid_x(p.x, p.m, 64, ctx->sg.cent, ctx->stream)
-                           : launch_group_centroid(ctx->ring_w(), p.order, p.m, ctx->cfg.depth, ctx->head,
-                                                   ctx->sg.cent, ctx->stream);
+        const int shift = ctx->cfg.guess_group_log2 ? ctx->cfg.guess_group_log2 : 6;
+        double3 *cent = shift > 6 ? ctx->sg.cent_big : ctx->sg.cent;
+        hipError_t e = hipSuccess;
+        if (p.x) {
+            e = launch_group_centroid_x(p.x, p.m, 1 << shift, cent, ctx->stream);
+        } else {
+            // centroids of 64 targets, merged into the larger groups
+            e = launch_group_centroid(ctx->ring_w(), p.order, p.m, ctx->cfg.depth, ctx->head, ctx->sg.cent,
+                                      ctx->stream);
+            if (e == hipSuccess && shift > 6)
+                e = launch_merge_centroids(ctx->sg.cent, p.m, 1 << (shift - 6), cent, ctx->stream);
+        }
         if (e != hipSuccess)
             return e;
         GuessParams gp{};
         gp.ring_w = ctx->ring_w();
         gp.ring_v = ctx->ring_v();
         gp.T = ctx->T();
-        gp.centroid = ctx->sg.cent;
+        gp.centroid = cent;
         gp.N = ctx->cfg.n;
-        gp.ngroups = (p.m + 63) / 64;
+        gp.ngroups = (p.m + (1 << shift) - 1) >> shift;
         gp.D = ctx->cfg.depth;
         gp.head = ctx->head;
         gp.inv_sigma = 1.0 / ctx->sg.sigma_ref;
         gp.ratio = 1;
         p.G = ctx->sg.G;
         p.g_groups = gp.ngroups;
-        p.g_shift = 6;
-        p.g_ratio = 1;
+        p.g_shift = shift;
         return launch_mlp_group_guess(ctx->sg.net, gp, ctx->sg.G, ctx->stream);
     });
 }
@@ -561,7 +571,8 @@ void empp_destroy(empp_ctx *ctx)
     for (hipEvent_t e : ctx->ev_pool)
         (void)hipEventDestroy(e);
     for (void *p : {(void *)ctx->sg.master, (void *)ctx->sg.m, (void *)ctx->sg.v, (void *)ctx->sg.grad,
-                    (void *)ctx->sg.part, (void *)ctx->sg.net, (void *)ctx->sg.G, (void *)ctx->sg.cent})
+                    (void *)ctx->sg.part, (void *)ctx->sg.net, (void *)ctx->sg.G, (void *)ctx->sg.cent,
+                    (void *)ctx->sg.cent_big})
         if (p)
             (void)hipFree(p);
     if (ctx->owns_ws && ctx->ws)
@@ -1138,6 +1149,7 @@ static empp_status surrogate_alloc(empp_ctx *ctx)
         {(void **)&ctx->sg.net, sizeof(MlpPacked)},
         {(void **)&ctx->sg.G, (size_t)ng * N * sizeof(float)},
         {(void **)&ctx->sg.cent, (size_t)ng * sizeof(double3)},
+        {(void **)&ctx->sg.cent_big, (size_t)ng * sizeof(double3)},
     };
     for (auto &w : want) {
         hipError_t e = hipMalloc(w.p, w.bytes);

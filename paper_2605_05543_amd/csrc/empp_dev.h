@@ -64,8 +64,9 @@ struct PairParams {
     double dt;
     const float *G;             // surrogate guesses G[source * g_groups + (a >> g_shift)]
     int64_t g_groups;           // target groups of the launch
-    int32_t g_shift;            // 6: one guess per 64 consecutive targets
-    int32_t g_ratio;            // G is a factor on the straight-line look-back
+    int32_t g_shift;            // guess mode 1: log2 of the targets per guess; mode 3: 0 (one per pair)
+    // guess modes: 0 bisection, 1 surrogate correction per target group,
+    // 2 straight-line look-back, 3 surrogate delay per pair, 4/5 warm start
     // warm start (step mode): bracket of every (source j, target slot a)
     // from the previous step at kc[j * m + a]: back offset b* (1..D-1) or
     // kBracketBefore.  Read by the warm-start search (kc_cold = 0) and

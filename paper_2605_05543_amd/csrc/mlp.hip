@@ -774,6 +774,35 @@ hipError_t launch_group_centroid(const double4 *ring_w, const int32_t *order, in
     return hipGetLastError();
 }
 
+// Centroids of groups of `ratio` consecutive 64-target groups (the last
+// ones may be short), weighted by their target counts.
+__global__ void merge_centroids_kernel(const double3 *cent64, int64_t m, int ratio, double3 *out)
+{
+    const int64_t n64 = (m + 63) / 64;
+    const int64_t grp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (grp * ratio >= n64)
+        return;
+    double sx = 0, sy = 0, sz = 0, wsum = 0;
+    for (int k = 0; k < ratio && grp * ratio + k < n64; ++k) {
+        const int64_t g = grp * ratio + k;
+        const double w = (double)(g + 1 < n64 ? 64 : m - 64 * g);
+        const double3 c = cent64[g];
+        sx += w * c.x;
+        sy += w * c.y;
+        sz += w * c.z;
+        wsum += w;
+    }
+    out[grp] = make_double3(sx / wsum, sy / wsum, sz / wsum);
+}
+
+hipError_t launch_merge_centroids(const double3 *cent64, int64_t m, int ratio, double3 *out, hipStream_t s)
+{
+    const int64_t ng = ((m + 63) / 64 + ratio - 1) / ratio;
+    hipLaunchKernelGGL(merge_centroids_kernel, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, cent64, m, ratio,
+                       out);
+    return hipGetLastError();
+}
+
 hipError_t launch_group_centroid_x(const double *x, int64_t m, int group, double3 *centroid, hipStream_t s)
 {
     int64_t ng = (m + group - 1) / group;

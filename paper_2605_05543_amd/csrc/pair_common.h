@@ -129,20 +129,4 @@ __device__ __forceinline__ int search_guided(Test test, int D, float guess, int 
     return lo;
 }
 
-// Closed-form look-back of a source coasting with velocity v from its
-// newest position: with R = r - w_n and beta = v/c, the light distance
-// s = c (t - t_r) solves (1 - beta^2) s^2 - 2 (R.beta) s - R^2 = 0.
-// Returns s / (c dt), the look-back in steps.
-__device__ inline float ballistic_steps(double Rx, double Ry, double Rz, double4 v, float inv_cdt)
-{
-    float rx = (float)Rx, ry = (float)Ry, rz = (float)Rz;
-    const float ic = (float)(1.0 / kC_LIGHT);
-    float bx = (float)v.x * ic, by = (float)v.y * ic, bz = (float)v.z * ic;
-    float rb = rx * bx + ry * by + rz * bz;
-    float r2 = rx * rx + ry * ry + rz * rz;
-    float g2 = 1.0f - (bx * bx + by * by + bz * bz);
-    float s = (rb + sqrtf(rb * rb + g2 * r2)) / g2;
-    return s * inv_cdt;
-}
-
 }  // namespace empp

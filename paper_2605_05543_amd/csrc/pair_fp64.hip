@@ -45,7 +45,7 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
 #define EMPP_BY_TILE(K, C, G, A) EMPP_LAUNCH(K, C, G, kLockstep, A)
 #define EMPP_BY_ADAPT(C, G) \
     do { if (p.ad) EMPP_LAUNCH(false, C, G, 1, true); else EMPP_BY_TILE(false, C, G, false); } while (0)
-    if (p.ad && (kstar || p.x || p.guess == 1))
+    if (p.ad && (kstar || p.x || p.guess == 1 || p.guess == 3))
         return hipErrorInvalidValue;  // the adaptive step is taken in step mode
     if (p.recon == 1) {
         // midpoint ablation: the paper's bisection, fixed step, any target mode
@@ -70,11 +70,15 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
     } else if (kstar) {
         if (p.guess == 2) {
             if (count) EMPP_BY_TILE(true, true, 2, false); else EMPP_BY_TILE(true, false, 2, false);
+        } else if (p.guess == 3) {
+            if (count) EMPP_BY_TILE(true, true, 3, false); else EMPP_BY_TILE(true, false, 3, false);
         } else if (p.guess == 1) {
             if (count) EMPP_BY_TILE(true, true, 1, false); else EMPP_BY_TILE(true, false, 1, false);
         } else {
             if (count) EMPP_BY_TILE(true, true, 0, false); else EMPP_BY_TILE(true, false, 0, false);
         }
+    } else if (p.guess == 3) {
+        if (count) EMPP_BY_TILE(false, true, 3, false); else EMPP_BY_TILE(false, false, 3, false);
     } else if (p.guess == 1) {
         if (count) EMPP_BY_TILE(false, true, 1, false); else EMPP_BY_TILE(false, false, 1, false);
     } else if (p.guess == 2) {

@@ -45,10 +45,16 @@ constexpr int kLockstep = 1;
 // light distances).
 inline int pair_nbuf(int D, int tile) { return (int64_t)tile * D <= kHalfRecs ? 2 : 1; }
 
+// Straight-line data of a staged tile's sources (guided searches): per
+// buffer and source {beta, 1 - beta^2} and {1 / (1 - beta^2), -, -, -};
+// then the surrogate's correction per buffer, wavefront and source.
+constexpr int kLineRecs = 2 * 2 * 4 + 2 * (kBlockFp64 / 64) * 4 / 4;
+
 inline size_t pair_lds_bytes(int D, int tile)
 {
     const size_t half = pair_nbuf(D, tile) == 2 ? kHalfRecs : (size_t)tile * D;
-    return (size_t)pair_nbuf(D, tile) * 2 * half * sizeof(double2) + (size_t)D * sizeof(double);
+    return (size_t)pair_nbuf(D, tile) * 2 * half * sizeof(double2) + (size_t)((D + 1) & ~1) * sizeof(double) +
+           kLineRecs * sizeof(float4);
 }
 
 // Sources per staged LDS tile for a history depth: as many as fill a
@@ -274,7 +280,7 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
             }
         }
     }
-    static_assert(!MIX || (!ADAPT && !MID && GUESS <= 2), "mixed precision: fixed step, no warm start");
+    static_assert(!MIX || (!ADAPT && !MID && GUESS <= 3), "mixed precision: fixed step, no warm start");
     // field sums: FP64 with Neumaier compensation, or FP32 with two-sum
     using Real = std::conditional_t<MIX, float, double>;
     Real sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
@@ -286,6 +292,7 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     // first (lowest) source of a failing pair; sources number below 2^31
     int32_t fail_j = INT32_MAX;
     const float inv_cdt = (float)(1.0 / (kC_LIGHT * p.dt));
+    const int64_t grp_index = a >> p.g_shift;  // surrogate group of this target
 
     // LDS: nbuf tile buffers, then the light distance of every logical slot
     // (shared by all sources).  A buffer holds its TS * D records as two
@@ -303,6 +310,12 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     const int hrec = nbuf == 2 ? kHalfRecs : TS * D;
     double2 *const halves = reinterpret_cast<double2 *>(lds);
     double *Ls = reinterpret_cast<double *>(halves + nbuf * 2 * hrec);
+    float4 *line = reinterpret_cast<float4 *>(Ls + ((D + 1) & ~1));
+    float *gcorr = reinterpret_cast<float *>(line + 2 * 2 * 4);  // [buffer][wavefront][source]
+    // guess mode 1: the surrogate's correction for groups of 64 or more
+    // targets (whole wavefronts) is staged with the tile; mode 3: one
+    // normalised delay per pair, read from the guess array
+    const bool stage_g = GUESS == 1;
     struct TileView {
         const double2 *xy, *zl;
         __device__ double4 rec(int i) const
@@ -349,6 +362,21 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
         }
     };
     auto stage = [&](int bi, int64_t jt, int ns, double4 r0, double4 r1) {
+        if ((GUESS == 1 || GUESS == 2) && tid < ns) {
+            // the source's newest velocity, for straight-line look-backs
+            const double4 vn = p.ring_v[(jt + tid) * D + p.head];
+            const double ic = 1.0 / kC_LIGHT;
+            const double bx = vn.x * ic, by = vn.y * ic, bz = vn.z * ic;
+            const double g2 = 1.0 - (bx * bx + by * by + bz * bz);
+            line[(bi * 4 + tid) * 2] = make_float4((float)bx, (float)by, (float)bz, (float)g2);
+            line[(bi * 4 + tid) * 2 + 1] = make_float4((float)(1.0 / g2), 0.0f, 0.0f, 0.0f);
+        }
+        if (stage_g && tid < (kBlockFp64 / 64) * 4) {
+            const int w = tid >> 2, sj = tid & 3;
+            const int64_t aw = (int64_t)bxi * kBlockFp64 + w * 64;
+            if (sj < ns && aw < p.m)
+                gcorr[(bi * (kBlockFp64 / 64) + w) * 4 + sj] = p.G[(jt + sj) * p.g_groups + (aw >> p.g_shift)];
+        }
         put(bi, ns, tid, r0);
         put(bi, ns, tid + kBlockFp64, r1);
         for (int q = tid + 2 * kBlockFp64; q < ns * D; q += kBlockFp64) {
@@ -594,23 +622,26 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
                     int b = -1;
                     if (valid[s]) {
                         auto test = [&](int bb) { return lightcone_positive(cur.rec(s * D + bb), rx, ry, rz); };
-                        double4 wn = cur.rec(s * D);
+                        const double4 wn = cur.rec(s * D);
+                        const float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
+                        const float r2 = Rx * Rx + Ry * Ry + Rz * Rz;
                         float g;
-                        if (GUESS == 2) {
-                            double4 vn = p.ring_v[jj[s] * D + p.head];
-                            g = ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
-                        } else if (p.g_ratio) {
+                        if (GUESS == 1 || GUESS == 2) {
+                            // straight-line look-back: with beta the source's
+                            // newest velocity / c, the positive root of
+                            // (1 - beta^2) s^2 - 2 (R.beta) s - R^2 = 0
+                            const float4 l0 = line[(cb * 4 + grp * S + s) * 2];
+                            const float ig2 = line[(cb * 4 + grp * S + s) * 2 + 1].x;
+                            const float rb = Rx * l0.x + Ry * l0.y + Rz * l0.z;
+                            g = (rb + __builtin_amdgcn_sqrtf(__builtin_fmaf(rb, rb, l0.w * r2))) * ig2 * inv_cdt;
                             // surrogate, one evaluation per group: the group's
-                            // correction factor to straight-line motion times
-                            // this target's straight-line look-back
-                            double4 vn = p.ring_v[jj[s] * D + p.head];
-                            float gh = p.G[jj[s] * p.g_groups + (a >> p.g_shift)];
-                            g = gh * ballistic_steps(rx - wn.x, ry - wn.y, rz - wn.z, vn, inv_cdt);
+                            // correction factor to straight-line motion
+                            if (GUESS == 1)
+                                g *= gcorr[(cb * (kBlockFp64 / 64) + (tid >> 6)) * 4 + grp * S + s];
                         } else {
                             // surrogate per pair: predicted c (t - t_r) / |r - w_n| times the distance
-                            float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
-                            float gh = p.G[jj[s] * p.g_groups + (a >> p.g_shift)];
-                            g = gh * __builtin_amdgcn_sqrtf(Rx * Rx + Ry * Ry + Rz * Rz) * inv_cdt;
+                            float gh = p.G[jj[s] * p.g_groups + grp_index];
+                            g = gh * __builtin_amdgcn_sqrtf(r2) * inv_cdt;
                         }
                         int fb = 0;
                         b = search_guided(test, D, g, 6, probes, fb);

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_mixed_kernel(PairParams p)
 hipError_t launch_pair_mixed(const PairParams &p0, hipStream_t stream, bool kstar, bool count)
 {
     PairParams p = p0;
-    if (p.guess > 2 || p.ad || p.recon == 1)
+    if (p.guess > 3 || p.ad || p.recon == 1)
         return hipErrorInvalidValue;  // fixed step, no warm start, linear reconstruction
     const int staged = pair_staged_tile(p.D);
     p.tile = kLockstep;
@@ -50,7 +50,8 @@ hipError_t launch_pair_mixed(const PairParams &p0, hipStream_t stream, bool ksta
     } while (0)
 #define EMPP_BY_GUESS(K, C)                                                                                  \
     do {                                                                                                    \
-        if (p.guess == 2) EMPP_LAUNCH(K, C, 2);                                                              \
+        if (p.guess == 3) EMPP_LAUNCH(K, C, 3);                                                              \
+        else if (p.guess == 2) EMPP_LAUNCH(K, C, 2);                                                         \
         else if (p.guess == 1) EMPP_LAUNCH(K, C, 1);                                                         \
         else EMPP_LAUNCH(K, C, 0);                                                                           \
     } while (0)

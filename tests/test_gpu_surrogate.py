@@ -193,3 +193,32 @@ def test_what_the_network_gains():
     assert rep["loss_last"] < 0.05 * rep["loss_first"]
     assert out["mlp-pair"][3] < 0.5 * out["bisect"][3]
     assert out["mlp-group"][3] < 0.5 * out["bisect"][3]
+
+
+@pytest.mark.parametrize("group_log2", [6, 10])
+def test_group_size_keeps_results(group_log2):
+    """Stepping with the network evaluated once per 64 or per 1024 targets:
+    the state after 6 steps is bit-identical to the bisection run."""
+    from paper_2605_05543_amd._lib import EMPP_GUESS_BISECT, EMPP_GUESS_MLP, Context
+
+    print(f"case surrogate group 2^{group_log2}", flush=True)
+    wl = bunch.C1
+    spec = bunch.BunchSpec(4096, (1e-3, 1e-3, 1e-3), 1.0, seed=31)
+    r, u = bunch.gaussian_bunch(spec)
+    out = {}
+    for guess in (EMPP_GUESS_BISECT, EMPP_GUESS_MLP):
+        with Context(n=4096, depth=wl.depth, q=Q, m=ME, dt=wl.dt, guess=guess, guess_group_log2=group_log2) as ctx:
+            ctx.init_bunch(r, u, 0.0)
+            ctx.init_history_straight()
+            ctx.surrogate_set(bunch.surrogate_init(7), bunch.sigma_ref_of(r))
+            ctx.step(5)
+            ctx.set_counting(True)
+            ctx.step(1)
+            c = ctx.counters()
+            out[guess] = (ctx.state(), ctx.fields(), c["probes"] / c["pairs"])
+    print(f"   sign tests per pair: bisection {out[EMPP_GUESS_BISECT][2]:.2f}, "
+          f"network per 2^{group_log2} targets {out[EMPP_GUESS_MLP][2]:.2f}", flush=True)
+    a, b = out[EMPP_GUESS_BISECT], out[EMPP_GUESS_MLP]
+    for x, y in zip(a[0] + a[1], b[0] + b[1]):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    assert b[2] < a[2]
