@@ -43,21 +43,32 @@ def measured_traffic():
     """HBM bytes per launch of the FP64 pair kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
     has changed since those counters were taken."""
-    import hashlib
     import re
 
     prof = os.path.join(ROOT, "profiles", "pair_fp64_c3_traffic.md")
-    src = os.path.join(ROOT, "paper_2605_05543_amd", "csrc", "pair_fp64.hip")
     try:
         text = open(prof).read()
     except OSError:
         return None
     m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    m_h = re.search(r"source: pair_fp64.hip sha256 ([0-9a-f]+)", text)
+    m_h = re.search(r"sources: " + " ".join(KERNEL_SOURCES) + r" sha256 ([0-9a-f]+)", text)
     if not (m_b and m_h):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return float(m_b.group(1)) if sha.startswith(m_h.group(1)) else None
+    return float(m_b.group(1)) if kernel_sources_sha().startswith(m_h.group(1)) else None
+
+
+# the sources the FP64 pair kernel is compiled from (traffic counters are
+# valid while they are unchanged)
+KERNEL_SOURCES = ("pair_fp64.hip", "pair_kernel.h", "pair_common.h", "empp_dev.h")
+
+
+def kernel_sources_sha():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2605_05543_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def log(*a):
