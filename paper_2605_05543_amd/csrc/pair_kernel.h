@@ -123,24 +123,26 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
     ok = ok && (en > 0.0) && (ev > 0.0);
     double inv = rcp64(en * ev);
     double ien = ev * inv, iev = en * inv;
-    double hx = ex * ien, hy = ey * ien, hz = ez * ien;
-    double px = c * hx - vrx, py = c * hy - vry, pz = c * hz - vrz;  // v'
-    double vv = vrx * vrx + vry * vry + vrz * vrz;
-    // eta x (v' x a)
-    double qx = py * az - pz * ay, qy = pz * ax - px * az, qz = px * ay - py * ax;
-    double rdx = ey * qz - ez * qy, rdy = ez * qx - ex * qz, rdz = ex * qy - ey * qx;
-    double pref = kq * en * (iev * iev * iev);
-    double cv = c2 - vv;
-    double Ex = pref * (cv * px + rdx);
-    double Ey = pref * (cv * py + rdy);
-    double Ez = pref * (cv * pz + rdz);
     const double ic = 1.0 / c;
+    const double icn = ien * ic;
+    double hx = ex * icn, hy = ey * icn, hz = ez * icn;  // eta_hat / c
+    double px = c2 * hx - vrx, py = c2 * hy - vry, pz = c2 * hz - vrz;  // v'
+    double vv = vrx * vrx + vry * vry + vrz * vrz;
+    // (c^2 - v^2) v' + eta x (v' x a), the cross product expanded as
+    // v' (eta . a) - a (eta . v') with eta . v' = ev
+    double ea = ex * ax + ey * ay + ez * az;
+    double pref = kq * en * (iev * iev * iev);
+    double k1 = pref * ((c2 - vv) + ea), k2 = pref * ev;
+    double Ex = k1 * px - k2 * ax;
+    double Ey = k1 * py - k2 * ay;
+    double Ez = k1 * pz - k2 * az;
     f[0] = Ex;
     f[1] = Ey;
     f[2] = Ez;
-    f[3] = (hy * Ez - hz * Ey) * ic;
-    f[4] = (hz * Ex - hx * Ez) * ic;
-    f[5] = (hx * Ey - hy * Ex) * ic;
+    // B = eta_hat x E / c
+    f[3] = hy * Ez - hz * Ey;
+    f[4] = hz * Ex - hx * Ez;
+    f[5] = hx * Ey - hy * Ex;
     eta_len = en;
     v_ret = make_double3(vrx, vry, vrz);
     return ok;
@@ -232,22 +234,24 @@ __device__ __forceinline__ bool lw_pair_mixed(double rx, double ry, double rz, d
     float ev = ex * px + ey * py + ez * pz;                           // eta . v' = c |eta| kappa
     ok = ok && ev > 0.0f;
     float iev = __builtin_amdgcn_rcpf(ev);
-    float hx = ex * ien, hy = ey * ien, hz = ez * ien;
+    const float icn = ien * (float)ic;
+    float hx = ex * icn, hy = ey * icn, hz = ez * icn;  // eta_hat / c
     // c^2 - |v_r|^2 from the FP64 value at v_1 plus the small correction
     float cv = C2 - df * (2.0f * (vx * gx + vy * gy + vz * gz) + df * (gx * gx + gy * gy + gz * gz));
-    float qx = py * az - pz * ay, qy = pz * ax - px * az, qz = px * ay - py * ax;
-    float rdx = ey * qz - ez * qy, rdy = ez * qx - ex * qz, rdz = ex * qy - ey * qx;
+    // eta x (v' x a) = v' (eta . a) - a (eta . v')
+    float ea = ex * ax + ey * ay + ez * az;
     float pref = kq * en * (iev * iev * iev);
-    float Ex = pref * (cv * px + rdx);
-    float Ey = pref * (cv * py + rdy);
-    float Ez = pref * (cv * pz + rdz);
-    const float icf = (float)ic;
+    float k1 = pref * (cv + ea), k2 = pref * ev;
+    float Ex = k1 * px - k2 * ax;
+    float Ey = k1 * py - k2 * ay;
+    float Ez = k1 * pz - k2 * az;
     f[0] = Ex;
     f[1] = Ey;
     f[2] = Ez;
-    f[3] = (hy * Ez - hz * Ey) * icf;
-    f[4] = (hz * Ex - hx * Ez) * icf;
-    f[5] = (hx * Ey - hy * Ex) * icf;
+    // B = eta_hat x E / c
+    f[3] = hy * Ez - hz * Ey;
+    f[4] = hz * Ex - hx * Ez;
+    f[5] = hx * Ey - hy * Ex;
     return ok;
 }
 
