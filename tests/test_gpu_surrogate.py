@@ -222,3 +222,45 @@ def test_group_size_keeps_results(group_log2):
     for x, y in zip(a[0] + a[1], b[0] + b[1]):
         assert np.array_equal(np.asarray(x), np.asarray(y))
     assert b[2] < a[2]
+
+
+def test_network_corrects_curving_histories():
+    """A bunch gyrating in a 0.5 T field (1 MeV: radius 9.5 mm, 2.9 mrad per
+    step; 0.74 rad over the 256 stored steps): the straight-line term misses
+    long look-backs by several slots.  The network, trained on pairs of this
+    state, corrects it from the features (the 4-step slope differs from the
+    newest velocity by the acceleration): fewer sign tests per pair than the
+    straight-line guess, with identical k* and fields."""
+    from paper_2605_05543_amd._lib import EMPP_GUESS_BALLISTIC, EMPP_GUESS_BISECT, EMPP_GUESS_MLP_PAIR, Context
+
+    print("case surrogate on gyrating histories", flush=True)
+    n, D, dt = 2048, 256, 1e-13
+    rng = np.random.default_rng(41)
+    r = 1e-3 * rng.standard_normal((3, n))
+    r[0] += 1.0
+    g = bunch.gamma_of_kinetic(bunch.MEV)
+    u = np.zeros((3, n))
+    u[1] = C * np.sqrt(g * g - 1.0)  # across the equatorial field
+    out = {}
+    with Context(n=n, depth=D, q=Q, m=ME, dt=dt, ext_field=1, dipole_b0=0.5, dipole_re=1.0) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        ctx.step(D + 20)  # every stored slot on the gyrating path
+        rg, _, t, _ = ctx.state()
+        ctx.surrogate_set(bunch.surrogate_init(8), bunch.sigma_ref_of(rg))
+        Xs, ys = ctx.surrogate_samples_torch(1 << 20, seed=5)
+        rep = ctx.surrogate_train_torch(Xs, ys, steps=1500, batch=8192, lr=3e-3, lr_final=3e-5)
+        print(f"   training: loss {rep['loss_first']:.3e} -> {rep['loss_last']:.3e}", flush=True)
+        for name, gm in (("bisect", EMPP_GUESS_BISECT), ("straight line", EMPP_GUESS_BALLISTIC),
+                         ("network per pair", EMPP_GUESS_MLP_PAIR)):
+            ctx.set_mode(0, gm)
+            ctx.set_counting(True)
+            E, B, k = ctx.fields_at(t, rg, np.arange(n), want_kstar=True)
+            c = ctx.counters()
+            out[name] = (E, B, k, c["probes"] / c["pairs"])
+            print(f"   {name}: {out[name][3]:.3f} sign tests per pair", flush=True)
+    for name in out:
+        assert np.array_equal(out[name][2], out["bisect"][2])
+        assert np.array_equal(out[name][0], out["bisect"][0]) and np.array_equal(out[name][1], out["bisect"][1])
+    assert out["straight line"][3] > 4.0  # the straight-line term misses
+    assert out["network per pair"][3] < 0.7 * out["straight line"][3]
