@@ -15,36 +15,51 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
 // Sources per staged LDS tile (used to size the source chunks).
 int pair_fp64_tile(int D) { return pair_staged_tile(D); }
 
+namespace {
+
+// One launch of a kernel instantiation: S sources per lockstep group,
+// staged / S groups per staged LDS tile.
+template <bool K, bool C, int G, int S, bool A, bool MID = false>
+void launch_one(PairParams p, int staged, size_t lds, dim3 grid, hipStream_t stream)
+{
+    p.tile = S;
+    p.groups = staged / S;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, C, G, S, A, MID>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S, A, MID>), grid, dim3(kBlockFp64), lds, stream, p);
+}
+
+// The lockstep width the search mode measured fastest with, where a staged
+// tile holds two sources; the adaptive reductions use one.
+template <bool K, bool C, int G, bool A>
+void launch_mode(const PairParams &p, int staged, size_t lds, dim3 grid, hipStream_t stream)
+{
+    if constexpr (!A && lockstep_sources(false, G) == 2) {
+        if (staged >= 2) {
+            launch_one<K, C, G, 2, A>(p, staged, lds, grid, stream);
+            return;
+        }
+    }
+    launch_one<K, C, G, 1, A>(p, staged, lds, grid, stream);
+}
+
+}  // namespace
+
 // Host-side launcher (called from the C ABI layer).
 hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar, bool count)
 {
     PairParams p = p0;
     const int staged = pair_staged_tile(p.D);
-    p.tile = kLockstep;
-    p.groups = staged / kLockstep;
     p.nbuf = pair_nbuf(p.D, staged);
     const int64_t nblocks = (p.m + kBlockFp64 - 1) / kBlockFp64 * p.nsplit;
     if (nblocks < 1 || nblocks > INT32_MAX)
         return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nblocks);
-    size_t lds = pair_lds_bytes(p.D, staged);
-#define EMPP_LAUNCH(K, C, G, S, A)                                                                           \
-    do {                                                                                                    \
-        if (lds > 65536)                                                                                    \
-            (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, C, G, S, A>,                        \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-        hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S, A>), grid, dim3(kBlockFp64), lds, stream, p);          \
-    } while (0)
-#define EMPP_LAUNCH_MID(K)                                                                                   \
-    do {                                                                                                    \
-        if (lds > 65536)                                                                                    \
-            (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, false, 0, 1, false, true>,          \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-        hipLaunchKernelGGL((pair_fp64_kernel<K, false, 0, 1, false, true>), grid, dim3(kBlockFp64), lds, stream, p); \
-    } while (0)
-#define EMPP_BY_TILE(K, C, G, A) EMPP_LAUNCH(K, C, G, kLockstep, A)
+    const size_t lds = pair_lds_bytes(p.D, staged);
+#define EMPP_MODE(K, C, G, A) launch_mode<K, C, G, A>(p, staged, lds, grid, stream)
 #define EMPP_BY_ADAPT(C, G) \
-    do { if (p.ad) EMPP_LAUNCH(false, C, G, 1, true); else EMPP_BY_TILE(false, C, G, false); } while (0)
+    do { if (p.ad) EMPP_MODE(false, C, G, true); else EMPP_MODE(false, C, G, false); } while (0)
     if (p.ad && (kstar || p.x || p.guess == 1 || p.guess == 3))
         return hipErrorInvalidValue;  // the adaptive step is taken in step mode
     if (p.recon == 1) {
@@ -52,9 +67,9 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
         if (p.ad || count)
             return hipErrorInvalidValue;
         if (kstar)
-            EMPP_LAUNCH_MID(true);
+            launch_one<true, false, 0, 1, false, true>(p, staged, lds, grid, stream);
         else
-            EMPP_LAUNCH_MID(false);
+            launch_one<false, false, 0, 1, false, true>(p, staged, lds, grid, stream);
         return hipGetLastError();
     }
     if (p.guess == 4) {
@@ -69,27 +84,25 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
         }
     } else if (kstar) {
         if (p.guess == 2) {
-            if (count) EMPP_BY_TILE(true, true, 2, false); else EMPP_BY_TILE(true, false, 2, false);
+            if (count) EMPP_MODE(true, true, 2, false); else EMPP_MODE(true, false, 2, false);
         } else if (p.guess == 3) {
-            if (count) EMPP_BY_TILE(true, true, 3, false); else EMPP_BY_TILE(true, false, 3, false);
+            if (count) EMPP_MODE(true, true, 3, false); else EMPP_MODE(true, false, 3, false);
         } else if (p.guess == 1) {
-            if (count) EMPP_BY_TILE(true, true, 1, false); else EMPP_BY_TILE(true, false, 1, false);
+            if (count) EMPP_MODE(true, true, 1, false); else EMPP_MODE(true, false, 1, false);
         } else {
-            if (count) EMPP_BY_TILE(true, true, 0, false); else EMPP_BY_TILE(true, false, 0, false);
+            if (count) EMPP_MODE(true, true, 0, false); else EMPP_MODE(true, false, 0, false);
         }
     } else if (p.guess == 3) {
-        if (count) EMPP_BY_TILE(false, true, 3, false); else EMPP_BY_TILE(false, false, 3, false);
+        if (count) EMPP_MODE(false, true, 3, false); else EMPP_MODE(false, false, 3, false);
     } else if (p.guess == 1) {
-        if (count) EMPP_BY_TILE(false, true, 1, false); else EMPP_BY_TILE(false, false, 1, false);
+        if (count) EMPP_MODE(false, true, 1, false); else EMPP_MODE(false, false, 1, false);
     } else if (p.guess == 2) {
         if (count) EMPP_BY_ADAPT(true, 2); else EMPP_BY_ADAPT(false, 2);
     } else {
         if (count) EMPP_BY_ADAPT(true, 0); else EMPP_BY_ADAPT(false, 0);
     }
 #undef EMPP_BY_ADAPT
-#undef EMPP_LAUNCH_MID
-#undef EMPP_BY_TILE
-#undef EMPP_LAUNCH
+#undef EMPP_MODE
     return hipGetLastError();
 }
 

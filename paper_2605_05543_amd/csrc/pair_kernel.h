@@ -33,11 +33,13 @@ namespace empp {
 // halves, then 32 KiB of {z, L^2} halves.
 constexpr int kHalfRecs = 2048;
 
-// Sources searched in lockstep by a thread.  One source per group with
-// several groups per staged tile measured faster than two in lockstep (at
-// N = 65536, D = 512: 39.0 against 41.3 ms for the bisection): the single
-// search needs fewer registers and the barrier is shared all the same.
-constexpr int kLockstep = 1;
+// Sources searched in lockstep by a thread, per search mode (measured at
+// N = 65536, D = 512): two for the straight-line guess and the warm start,
+// whose short searches leave room for a second one in flight; one for the
+// bisection and the surrogate modes, where the second search's registers
+// cost more than its overlap gains (FP64 bisection 37.1 ms with one, 37.8
+// with two; warm start 32.2 and 31.2).
+constexpr int lockstep_sources(bool mix, int guess) { return guess == 2 || (!mix && guess == 4) ? 2 : 1; }
 
 // LDS buffers: two of 64 KiB (staging overlapped with the search) while a
 // staged tile fits in kHalfRecs records, else one sized to the tile
@@ -626,13 +628,12 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
                         if (valid[s])
                             p.kc[jj[s] * p.m + a] = bk[s] < 0 ? kBracketBefore : (uint16_t)bk[s];
                 }
-                double4 v1[S], v2[S];
 #pragma unroll
-                for (int s = 0; s < S; ++s)
-                    load_v(s, bk[s], v1[s], v2[s]);
-#pragma unroll
-                for (int s = 0; s < S; ++s)
-                    finish(s, bk[s], v1[s], v2[s]);
+                for (int s = 0; s < S; ++s) {
+                    double4 v1, v2;
+                    load_v(s, bk[s], v1, v2);
+                    finish(s, bk[s], v1, v2);
+                }
             } else {
                 // guided searches, one source at a time
 #pragma unroll

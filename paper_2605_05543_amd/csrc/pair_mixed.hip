@@ -21,11 +21,38 @@ namespace empp {
 
 extern const bool kHaveMixed = true;
 
-template <bool KSTAR, bool COUNT, int GUESS>
+template <bool KSTAR, bool COUNT, int GUESS, int S>
 __global__ __launch_bounds__(kBlockFp64, 4) void pair_mixed_kernel(PairParams p)
 {
-    pair_body<true, KSTAR, COUNT, GUESS, kLockstep, false, false>(p);
+    pair_body<true, KSTAR, COUNT, GUESS, S, false, false>(p);
 }
+
+namespace {
+
+template <bool K, bool C, int G, int S>
+void launch_one(PairParams p, int staged, size_t lds, dim3 grid, hipStream_t stream)
+{
+    p.tile = S;
+    p.groups = staged / S;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)pair_mixed_kernel<K, C, G, S>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((pair_mixed_kernel<K, C, G, S>), grid, dim3(kBlockFp64), lds, stream, p);
+}
+
+template <bool K, bool C, int G>
+void launch_mode(const PairParams &p, int staged, size_t lds, dim3 grid, hipStream_t stream)
+{
+    if constexpr (lockstep_sources(true, G) == 2) {
+        if (staged >= 2) {
+            launch_one<K, C, G, 2>(p, staged, lds, grid, stream);
+            return;
+        }
+    }
+    launch_one<K, C, G, 1>(p, staged, lds, grid, stream);
+}
+
+}  // namespace
 
 hipError_t launch_pair_mixed(const PairParams &p0, hipStream_t stream, bool kstar, bool count)
 {
@@ -33,27 +60,18 @@ hipError_t launch_pair_mixed(const PairParams &p0, hipStream_t stream, bool ksta
     if (p.guess > 3 || p.ad || p.recon == 1)
         return hipErrorInvalidValue;  // fixed step, no warm start, linear reconstruction
     const int staged = pair_staged_tile(p.D);
-    p.tile = kLockstep;
-    p.groups = staged / kLockstep;
     p.nbuf = pair_nbuf(p.D, staged);
     const int64_t nblocks = (p.m + kBlockFp64 - 1) / kBlockFp64 * p.nsplit;
     if (nblocks < 1 || nblocks > INT32_MAX)
         return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nblocks);
-    size_t lds = pair_lds_bytes(p.D, staged);
-#define EMPP_LAUNCH(K, C, G)                                                                                 \
-    do {                                                                                                    \
-        if (lds > 65536)                                                                                    \
-            (void)hipFuncSetAttribute((const void *)pair_mixed_kernel<K, C, G>,                             \
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
-        hipLaunchKernelGGL((pair_mixed_kernel<K, C, G>), grid, dim3(kBlockFp64), lds, stream, p);           \
-    } while (0)
+    const size_t lds = pair_lds_bytes(p.D, staged);
 #define EMPP_BY_GUESS(K, C)                                                                                  \
     do {                                                                                                    \
-        if (p.guess == 3) EMPP_LAUNCH(K, C, 3);                                                              \
-        else if (p.guess == 2) EMPP_LAUNCH(K, C, 2);                                                         \
-        else if (p.guess == 1) EMPP_LAUNCH(K, C, 1);                                                         \
-        else EMPP_LAUNCH(K, C, 0);                                                                           \
+        if (p.guess == 3) launch_mode<K, C, 3>(p, staged, lds, grid, stream);                                \
+        else if (p.guess == 2) launch_mode<K, C, 2>(p, staged, lds, grid, stream);                           \
+        else if (p.guess == 1) launch_mode<K, C, 1>(p, staged, lds, grid, stream);                           \
+        else launch_mode<K, C, 0>(p, staged, lds, grid, stream);                                             \
     } while (0)
     if (kstar) {
         if (count) EMPP_BY_GUESS(true, true); else EMPP_BY_GUESS(true, false);
@@ -61,7 +79,6 @@ hipError_t launch_pair_mixed(const PairParams &p0, hipStream_t stream, bool ksta
         if (count) EMPP_BY_GUESS(false, true); else EMPP_BY_GUESS(false, false);
     }
 #undef EMPP_BY_GUESS
-#undef EMPP_LAUNCH
     return hipGetLastError();
 }
 
