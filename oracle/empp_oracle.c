@@ -88,26 +88,43 @@ static void neumaier_add(double *sum, double *comp, double x)
 
 /* ---- Sec. 2.2: light-cone sign of a stored sample --------------------------
  * f_k = c (t - T_k) - |r - w_k|.  The bracket needs only its sign; it is
- * evaluated on squares so no square root enters the decision:
- *   f_k > 0  <=>  L*L - dx*dx - dy*dy - dz*dz > 0,   L = c*(t - T_k),
- * with L*L rounded once and the three squares taken off by fused
- * multiply-adds (C99 fma: one rounding each), in the order x, y, z.  The
- * expression is fixed (and the build forbids other contraction) so that
- * the GPU path can reproduce the decision bit for bit.                      */
-static int lightcone_positive(const double r[3], const double wk[3], double t, double Tk)
+ * taken on squares so no square root enters the decision.  With the
+ * source's newest sample w_n, the target's offset d0 = r - w_n and the
+ * sample's offset D_k = w_n - w_k, |r - w_k|^2 = |d0|^2 + 2 d0.D_k + |D_k|^2,
+ * so with L = c (t - T_k)
+ *   f_k > 0  <=>  A_k - 2 d0.D_k > |d0|^2,   A_k = L^2 - |D_k|^2.
+ * A_k belongs to the sample alone and |d0|^2 to the pair alone.  Fixed
+ * evaluation (C99 fma, one rounding each, the build forbids other
+ * contraction): A = L*L, then the squares of D_x, D_y, D_z taken off by
+ * fma in that order; q = A, then d0_x (-2 D_x), d0_y (-2 D_y), d0_z (-2 D_z)
+ * added by fma; R = d0_x d0_x, then d0_y d0_y and d0_z d0_z added by fma;
+ * the sample is inside the past light cone when q > R.  The GPU path
+ * evaluates the same expression and reproduces the decision bit for bit.   */
+static double offset_sq(const double d0[3])
+{
+    double R = d0[0] * d0[0];
+    R = fma(d0[1], d0[1], R);
+    return fma(d0[2], d0[2], R);
+}
+
+static int lightcone_positive(const double d0[3], double R0sq, const double wn[3], const double wk[3],
+                              double t, double Tk)
 {
     double L = C_LIGHT * (t - Tk);
-    double dx = r[0] - wk[0];
-    double dy = r[1] - wk[1];
-    double dz = r[2] - wk[2];
-    double q = L * L;
-    q = fma(-dx, dx, q);
-    q = fma(-dy, dy, q);
-    q = fma(-dz, dz, q);
+    double Dx = wn[0] - wk[0];
+    double Dy = wn[1] - wk[1];
+    double Dz = wn[2] - wk[2];
+    double A = L * L;
+    A = fma(-Dx, Dx, A);
+    A = fma(-Dy, Dy, A);
+    A = fma(-Dz, Dz, A);
+    double q = fma(d0[0], -2.0 * Dx, A);
+    q = fma(d0[1], -2.0 * Dy, q);
+    q = fma(d0[2], -2.0 * Dz, q);
 #ifdef MUT_TIE_NEWER
-    return q >= 0.0;
+    return q >= R0sq;
 #else
-    return q > 0.0;
+    return q > R0sq;
 #endif
 }
 
@@ -171,10 +188,14 @@ static int solve_retarded(int64_t N, int32_t ns, const double *T, const double *
                           retarded_t *out)
 {
     int32_t ks = -1;
+    double wn[3];
+    load_sample(w, N, ns - 1, j, wn);
+    const double d0[3] = {r[0] - wn[0], r[1] - wn[1], r[2] - wn[2]};
+    const double R0sq = offset_sq(d0);
     for (int32_t s = ns - 2; s >= 0; --s) {
         double wk[3];
         load_sample(w, N, s, j, wk);
-        if (lightcone_positive(r, wk, t, T[s])) {
+        if (lightcone_positive(d0, R0sq, wn, wk, t, T[s])) {
             ks = s;
             break;
         }

@@ -524,13 +524,12 @@ __device__ void pair_features(const SampleParams &p, int64_t i, int64_t j, float
     Xrow[8] = (float)((wn.z - w4.z) / span);
     Xrow[9] = 0.0f;  // log1p((t - T_n)/dt) with t = T_n
     // exact bracket (FP64 sign tests on the history in HBM) and root
+    const double R0sq = offset_sq(Rx, Ry, Rz);
     auto test = [&](int b) {
         int ph = h - b;
         ph += ph < 0 ? D : 0;
-        double4 w = p.ring_w[j * D + ph];
-        double L = c * (p.t - p.T[ph]);
-        w.w = L * L;
-        return lightcone_positive(w, r.x, r.y, r.z);
+        const double L = c * (p.t - p.T[ph]);
+        return lightcone_positive(lightcone_record(wn, p.ring_w[j * D + ph], L), Rx, Ry, Rz, R0sq);
     };
     int probes = 0;
     int b = search_bisect(test, D, probes);

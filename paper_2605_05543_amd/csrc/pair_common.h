@@ -6,21 +6,39 @@
 
 namespace empp {
 
-// Staged history record of one source at one logical slot:
-// {x, y, z, L2} with L2 = L*L (rounded once), L = c (t - T_k) the light
-// distance back to the slot.  The sign test f_k > 0 is
-// L2 - dx*dx - dy*dy - dz*dz > 0 with the three squares taken off by fused
-// multiply-adds in the order x, y, z: one rounding per step, the same
-// decision as any IEEE evaluation of that expression.
-__device__ inline bool lightcone_positive(double4 rec, double rx, double ry, double rz)
+// Light-cone sign of a stored sample (Sec. 2.2), split into a part of the
+// sample and a part of the pair.  With the source's newest sample w_n, the
+// target's offset d0 = r - w_n and the sample's offset D = w_n - w_k,
+// |r - w_k|^2 = |d0|^2 + 2 d0.D + |D|^2, so with L = c (t - T_k)
+//   f_k > 0  <=>  A - 2 d0.D > |d0|^2,   A = L^2 - |D|^2.
+// The staged record of a sample is {-2 D, A}; a test is then three fused
+// multiply-adds and a compare.  Every step is one rounding in a fixed
+// order (A = L*L, minus D_x^2, D_y^2, D_z^2 by FMA; q = A plus d0_x (-2 D_x),
+// y, z by FMA; |d0|^2 = d0_x^2 plus d0_y^2, d0_z^2 by FMA), the same
+// decision as the CPU reference of the method.
+__device__ inline double4 lightcone_record(double4 wn, double4 wk, double L)
 {
-    double dx = rx - rec.x;
-    double dy = ry - rec.y;
-    double dz = rz - rec.z;
-    double q = __builtin_fma(-dx, dx, rec.w);
-    q = __builtin_fma(-dy, dy, q);
-    q = __builtin_fma(-dz, dz, q);
-    return q > 0.0;
+    const double Dx = wn.x - wk.x, Dy = wn.y - wk.y, Dz = wn.z - wk.z;
+    double A = L * L;
+    A = __builtin_fma(-Dx, Dx, A);
+    A = __builtin_fma(-Dy, Dy, A);
+    A = __builtin_fma(-Dz, Dz, A);
+    return make_double4(-2.0 * Dx, -2.0 * Dy, -2.0 * Dz, A);
+}
+
+__device__ inline double offset_sq(double d0x, double d0y, double d0z)
+{
+    double R = d0x * d0x;
+    R = __builtin_fma(d0y, d0y, R);
+    return __builtin_fma(d0z, d0z, R);
+}
+
+__device__ inline bool lightcone_positive(double4 rec, double d0x, double d0y, double d0z, double R0sq)
+{
+    double q = __builtin_fma(d0x, rec.x, rec.w);
+    q = __builtin_fma(d0y, rec.y, q);
+    q = __builtin_fma(d0z, rec.z, q);
+    return q > R0sq;
 }
 
 // Bisection of the paper: test the oldest sample first (if it is not

@@ -29,17 +29,16 @@
 
 namespace empp {
 
-// Records per half-array of a double-buffered LDS tile: 32 KiB of {x, y}
-// halves, then 32 KiB of {z, L^2} halves.
+// Records per half-array of a double-buffered LDS tile: 32 KiB of the
+// records' first 16-byte halves, then 32 KiB of their second halves.
 constexpr int kHalfRecs = 2048;
 
 // Sources searched in lockstep by a thread, per search mode (measured at
-// N = 65536, D = 512): two for the straight-line guess and the warm start,
-// whose short searches leave room for a second one in flight; one for the
-// bisection and the surrogate modes, where the second search's registers
-// cost more than its overlap gains (FP64 bisection 37.1 ms with one, 37.8
-// with two; warm start 32.2 and 31.2).
-constexpr int lockstep_sources(bool mix, int guess) { return guess == 2 || (!mix && guess == 4) ? 2 : 1; }
+// N = 65536, D = 512): two for the mixed path's straight-line guess, whose
+// short search leaves room for a second one in flight; one elsewhere, where
+// the second search's registers cost more than its overlap gains (FP64
+// warm start 31.3 ms with one, 37.2 with two, which spill).
+constexpr int lockstep_sources(bool mix, int guess) { return mix && guess == 2 ? 2 : 1; }
 
 // LDS buffers: two of 64 KiB (staging overlapped with the search) while a
 // staged tile fits in kHalfRecs records, else one sized to the tile
@@ -47,10 +46,11 @@ constexpr int lockstep_sources(bool mix, int guess) { return guess == 2 || (!mix
 // light distances).
 inline int pair_nbuf(int D, int tile) { return (int64_t)tile * D <= kHalfRecs ? 2 : 1; }
 
-// Straight-line data of a staged tile's sources (guided searches): per
-// buffer and source {beta, 1 - beta^2} and {1 / (1 - beta^2), -, -, -};
-// then the surrogate's correction per buffer, wavefront and source.
-constexpr int kLineRecs = 2 * 2 * 4 + 2 * (kBlockFp64 / 64) * 4 / 4;
+// Per-source data of the staged tiles, in 16-byte units: the straight-line
+// data of the guided searches (per buffer and source {beta, 1 - beta^2} and
+// {1 / (1 - beta^2), -, -, -}), the surrogate's correction per buffer,
+// wavefront and source, and the newest samples w_n of three tiles' sources.
+constexpr int kLineRecs = 2 * 2 * 4 + 2 * (kBlockFp64 / 64) * 4 / 4 + 3 * 4 * 2;
 
 inline size_t pair_lds_bytes(int D, int tile)
 {
@@ -81,17 +81,17 @@ __device__ inline double sqrt_pos(double x)
 }
 
 // Retarded root, reconstruction and LW field of one pair (Eqs. dt,
-// linear, linear2, LW_E, LW_B).  w1 = {x, y, z, -} is the bracket's older
-// sample, L1 = c (t - t_1); v1 = {v_1, 1/(t_2 - t_1)}, v2 = {v_2, -} the
-// velocity records of the bracket ends.  Writes E and B into f[0..5].
-// Returns false on a numerical failure (negative discriminant, eta <= 0).
-__device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, double L1, double4 v1, double4 v2,
-                               bool before, double kq, double f[6], double &eta_len, double3 &v_ret, bool mid,
-                               double4 w2)
+// linear, linear2, LW_E, LW_B).  (dx, dy, dz) = r - w_1, the target's
+// offset from the bracket's older sample, L1 = c (t - t_1);
+// v1 = {v_1, 1/(t_2 - t_1)}, v2 = {v_2, -} the velocity records of the
+// bracket ends; dw = w_2 - w_1 (midpoint ablation only).  Writes E and B
+// into f[0..5].  Returns false on a numerical failure (negative
+// discriminant, eta <= 0).
+__device__ inline bool lw_pair(double dx, double dy, double dz, double L1, double4 v1, double4 v2, bool before,
+                               double kq, double f[6], double &eta_len, double3 &v_ret, bool mid, double3 dw)
 {
     const double c = kC_LIGHT;
     const double c2 = c * c;
-    double dx = rx - w1.x, dy = ry - w1.y, dz = rz - w1.z;
     // C2 dt^2 + 2 C1h dt + C0 = 0 (Eq. dt with C1 = 2 C1h); the physical
     // root -(C1h + sqrt(C1h^2 - C2 C0))/C2 in Vieta's form.
     double C2 = c2 - (v1.x * v1.x + v1.y * v1.y + v1.z * v1.z);
@@ -112,9 +112,9 @@ __device__ inline bool lw_pair(double rx, double ry, double rz, double4 w1, doub
     double en = L1 - c * dtr;
     if (mid && !before) {
         // Eq. (mid): the bracket ends' means, eta = r - (w_1 + w_2)/2
-        ex = dx - 0.5 * (w2.x - w1.x);
-        ey = dy - 0.5 * (w2.y - w1.y);
-        ez = dz - 0.5 * (w2.z - w1.z);
+        ex = dx - 0.5 * dw.x;
+        ey = dy - 0.5 * dw.y;
+        ez = dz - 0.5 * dw.z;
         en = sqrt(ex * ex + ey * ey + ez * ez);
         vrx = 0.5 * (v1.x + v2.x);
         vry = 0.5 * (v1.y + v2.y);
@@ -161,7 +161,8 @@ __device__ inline void two_sum(float &s, float &e, float x)
 }
 
 struct MixedPair {
-    double4 w1, v1, v2;  // FP64 records of the bracket (global memory)
+    double3 d;           // r - w_1, the target's offset from the bracket's older sample
+    double4 v1, v2;      // FP64 velocity records of the bracket ends
 };
 
 // Root, reconstruction and LW field from FP64 inputs.  The coefficients of
@@ -178,14 +179,14 @@ struct MixedPair {
 // pays in the bisection pass, 43.2 -> 36.7 ms at N = 65536, D = 512; the
 // guided passes are 1-2 % faster with the compiler's choice).
 template <bool BRANCH_RESCUE>
-__device__ __forceinline__ bool lw_pair_mixed(double rx, double ry, double rz, double L1d, MixedPair q, bool before,
+__device__ __forceinline__ bool lw_pair_mixed(double L1d, MixedPair q, bool before,
                                               float kq, float f[6], bool &rescued)
 {
     const double c = kC_LIGHT;
     const double ic = 1.0 / kC_LIGHT;
     const float cf = (float)kC_LIGHT;
     // FP64: offset to the bracket sample and the quadratic's coefficients
-    double dxd = rx - q.w1.x, dyd = ry - q.w1.y, dzd = rz - q.w1.z;
+    double dxd = q.d.x, dyd = q.d.y, dzd = q.d.z;
     double C0d = L1d * L1d - (dxd * dxd + dyd * dyd + dzd * dzd);
     double C2d = c * c - (q.v1.x * q.v1.x + q.v1.y * q.v1.y + q.v1.z * q.v1.z);
     double C1hd = (dxd * q.v1.x + dyd * q.v1.y + dzd * q.v1.z) - c * L1d;
@@ -315,8 +316,9 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     const int64_t grp_index = a >> p.g_shift;  // surrogate group of this target
 
     // LDS: nbuf tile buffers, then the light distance of every logical slot
-    // (shared by all sources).  A buffer holds its TS * D records as two
-    // arrays of 16-byte halves, {x, y} then {z, L^2}, hrec halves apart:
+    // (shared by all sources).  A buffer holds its TS * D records
+    // {-2 D, A} of the split sign test (lightcone_record) as two arrays of
+    // 16-byte halves, {-2 D_x, -2 D_y} then {-2 D_z, A}, hrec halves apart:
     // lanes that probe different slots then spread over twice as many LDS
     // bank groups as with 32-byte records.  With two buffers the distance is
     // the fixed kHalfRecs, so a probe's two reads share one address (the
@@ -332,6 +334,21 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     double *Ls = reinterpret_cast<double *>(halves + nbuf * 2 * hrec);
     float4 *line = reinterpret_cast<float4 *>(Ls + ((D + 1) & ~1));
     float *gcorr = reinterpret_cast<float *>(line + 2 * 2 * 4);  // [buffer][wavefront][source]
+    // newest samples w_n of the sources of three consecutive staged tiles
+    // (tile i in slot i % 3), as {x, y}, {z, -}: written two tiles ahead of
+    // the tile's search, read when its records are staged and searched
+    double2 *wnr = reinterpret_cast<double2 *>(gcorr + 2 * (kBlockFp64 / 64) * 4);
+    auto write_wn = [&](int it_tile, int64_t jt, int ns) {
+        if (tid < ns) {
+            const double4 w = p.ring_w[(jt + tid) * D + p.head];
+            wnr[((it_tile % 3) * 4 + tid) * 2] = make_double2(w.x, w.y);
+            wnr[((it_tile % 3) * 4 + tid) * 2 + 1] = make_double2(w.z, 0.0);
+        }
+    };
+    auto read_wn = [&](int it_tile, int s) {
+        const double2 a = wnr[((it_tile % 3) * 4 + s) * 2], b = wnr[((it_tile % 3) * 4 + s) * 2 + 1];
+        return make_double4(a.x, a.y, b.x, 0.0);
+    };
     // guess mode 1: the surrogate's correction for groups of 64 or more
     // targets (whole wavefronts) is staged with the tile; mode 3: one
     // normalised delay per pair, read from the guess array
@@ -371,17 +388,17 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
         }
         return w;
     };
-    auto put = [&](int bi, int ns, int q, double4 w) {
+    auto put = [&](int bi, int it_tile, int ns, int q, double4 w) {
         int s = src_of(q);
         int b = q - s * D;
         if (b < D && s < ns) {
-            double L = Ls[b];
+            const double4 rec = lightcone_record(read_wn(it_tile, s), w, Ls[b]);
             double2 *xy = halves + bi * 2 * hrec + s * D + b;
-            xy[0] = make_double2(w.x, w.y);
-            xy[hrec] = make_double2(w.z, L * L);
+            xy[0] = make_double2(rec.x, rec.y);
+            xy[hrec] = make_double2(rec.z, rec.w);
         }
     };
-    auto stage = [&](int bi, int64_t jt, int ns, double4 r0, double4 r1) {
+    auto stage = [&](int bi, int it_tile, int64_t jt, int ns, double4 r0, double4 r1) {
         if ((GUESS == 1 || GUESS == 2) && tid < ns) {
             // the source's newest velocity, for straight-line look-backs
             const double4 vn = p.ring_v[(jt + tid) * D + p.head];
@@ -397,13 +414,13 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
             if (sj < ns && aw < p.m)
                 gcorr[(bi * (kBlockFp64 / 64) + w) * 4 + sj] = p.G[(jt + sj) * p.g_groups + (aw >> p.g_shift)];
         }
-        put(bi, ns, tid, r0);
-        put(bi, ns, tid + kBlockFp64, r1);
+        put(bi, it_tile, ns, tid, r0);
+        put(bi, it_tile, ns, tid + kBlockFp64, r1);
         for (int q = tid + 2 * kBlockFp64; q < ns * D; q += kBlockFp64) {
             int s = q / D, b = q - (q / D) * D;
             int ph = p.head - b;
             ph += ph < 0 ? D : 0;
-            put(bi, ns, q, p.ring_w[(jt + s) * D + ph]);
+            put(bi, it_tile, ns, q, p.ring_w[(jt + s) * D + ph]);
         }
     };
     auto tile_size = [&](int64_t jt) { return (int)((j1 - jt) < TS ? (j1 - jt) : TS); };
@@ -416,9 +433,14 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     // barrier per tile both publishes tile i + 1 and retires tile i's
     // buffer for tile i + 2.  One buffer (deep histories): stage, then
     // search, with a barrier on either side.
+    if (j0 < j1) {
+        write_wn(0, j0, tile_size(j0));
+        if (nbuf == 2 && j0 + TS < j1)
+            write_wn(1, j0 + TS, tile_size(j0 + TS));
+    }
     if (nbuf == 2 && j0 < j1) {
         __syncthreads();
-        stage(0, j0, tile_size(j0), pf0, pf1);
+        stage(0, 0, j0, tile_size(j0), pf0, pf1);
         if (j0 + TS < j1) {
             pf0 = fetch(j0 + TS, tile_size(j0 + TS), tid);
             pf1 = fetch(j0 + TS, tile_size(j0 + TS), tid + kBlockFp64);
@@ -439,19 +461,21 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
         const int cb = nbuf == 2 ? (it & 1) : 0;
         if (nbuf == 2) {
             if (jts + TS < j1) {
-                stage(cb ^ 1, jts + TS, tile_size(jts + TS), pf0, pf1);
+                stage(cb ^ 1, it + 1, jts + TS, tile_size(jts + TS), pf0, pf1);
                 if (jts + 2 * TS < j1) {
                     pf0 = fetch(jts + 2 * TS, tile_size(jts + 2 * TS), tid);
                     pf1 = fetch(jts + 2 * TS, tile_size(jts + 2 * TS), tid + kBlockFp64);
+                    write_wn(it + 2, jts + 2 * TS, tile_size(jts + 2 * TS));
                 }
             }
         } else {
             __syncthreads();
-            stage(0, jts, tile_size(jts), pf0, pf1);
+            stage(0, it, jts, tile_size(jts), pf0, pf1);
             __syncthreads();
             if (jts + TS < j1) {
                 pf0 = fetch(jts + TS, tile_size(jts + TS), tid);
                 pf1 = fetch(jts + TS, tile_size(jts + TS), tid + kBlockFp64);
+                write_wn(it + 1, jts + TS, tile_size(jts + TS));
             }
         }
       for (int grp = 0; grp < G && jts + grp * S < j1; ++grp) {
@@ -469,19 +493,27 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
             bool valid[S];
             int64_t jj[S];
             int bk[S];
+            // the target's offset d0 = r - w_n from each source's newest
+            // sample, and |d0|^2 (the pair's part of the sign test)
+            double d0x[S], d0y[S], d0z[S], R0[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 jj[s] = jt + (s < ns ? s : 0);
                 valid[s] = s < ns && jj[s] != self;
                 if (KSTAR && s < ns && jj[s] == self)
                     p.kstar[a * p.n_src + jj[s]] = 0;
+                const double4 wn = read_wn(it, grp * S + s);
+                d0x[s] = rx - wn.x;
+                d0y[s] = ry - wn.y;
+                d0z[s] = rz - wn.z;
+                R0[s] = offset_sq(d0x[s], d0y[s], d0z[s]);
                 // a target on the source's present position: eta = 0
-                double4 wn = cur.rec(s * D);
-                if (valid[s] && rx == wn.x && ry == wn.y && rz == wn.z) {
+                if (valid[s] && d0x[s] == 0.0 && d0y[s] == 0.0 && d0z[s] == 0.0) {
                     fail_j = min(fail_j, (int32_t)jj[s]);
                     valid[s] = false;
                 }
             }
+            auto inside_cone = [&](int s, double4 rec) { return lightcone_positive(rec, d0x[s], d0y[s], d0z[s], R0[s]); };
 
             // bracket velocity records (they carry 1/(t_2 - t_1)), root,
             // reconstruction, LW field and accumulation of tile source s
@@ -503,15 +535,23 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
                 double en = 0.0;
                 double3 vr = make_double3(0.0, 0.0, 0.0);
                 bool ok;
+                // r - w_1 = d0 + D from the staged -2 D
+                const double4 r1 = cur.rec(s * D + bb);
+                const double3 d1 = make_double3(__builtin_fma(-0.5, r1.x, d0x[s]), __builtin_fma(-0.5, r1.y, d0y[s]),
+                                                __builtin_fma(-0.5, r1.z, d0z[s]));
                 if constexpr (MIX) {
                     bool resc = false;
-                    ok = lw_pair_mixed<GUESS == 0>(rx, ry, rz, Ls[bb], MixedPair{cur.rec(s * D + bb), v1, v2}, before, kqf, f,
-                                       resc);
+                    ok = lw_pair_mixed<GUESS == 0>(Ls[bb], MixedPair{d1, v1, v2}, before, kqf, f, resc);
                     if (COUNT && valid[s])
                         nresc += resc ? 1 : 0;
                 } else {
-                    ok = lw_pair(rx, ry, rz, cur.rec(s * D + bb), Ls[bb], v1, v2, before, p.kq, f, en, vr, MID,
-                                 MID ? cur.rec(s * D + (bb > 0 ? bb - 1 : 0)) : make_double4(0.0, 0.0, 0.0, 0.0));
+                    double3 dw = make_double3(0.0, 0.0, 0.0);
+                    if (MID) {
+                        // w_2 - w_1 = D_1 - D_2 from the staged -2 D of both ends
+                        const double4 r2 = cur.rec(s * D + (bb > 0 ? bb - 1 : 0));
+                        dw = make_double3(-0.5 * (r1.x - r2.x), -0.5 * (r1.y - r2.y), -0.5 * (r1.z - r2.z));
+                    }
+                    ok = lw_pair(d1.x, d1.y, d1.z, Ls[bb], v1, v2, before, p.kq, f, en, vr, MID, dw);
                 }
                 if (valid[s]) {
                     if (ok) {
@@ -545,12 +585,12 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
                     // LDS byte address of the record of xb: f(xb) <= 0, the
                     // bracket lies in (xb, xb + n]
                     uint32_t xo[S];
-                    // LDS byte address of the group's first {x, y} half
+                    // LDS byte address of the group's first record (its first half)
                     const uint32_t xy0 =
                         lds_base + (uint32_t)(cb * 2 * hrec + grp * S * D) * (uint32_t)sizeof(double2);
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        inside[s] = lightcone_positive(cur.rec(s * D + D - 1), rx, ry, rz);
+                        inside[s] = inside_cone(s, cur.rec(s * D + D - 1));
                         xo[s] = xy0 + (uint32_t)(s * D) * (uint32_t)sizeof(double2);
                     }
                     bool any = false;
@@ -570,7 +610,7 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
                                 const dv2 vb =
                                     *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)(mo + (uint32_t)zl_off);
                                 const double4 rec = make_double4(va.x, va.y, vb.x, vb.y);
-                                xo[s] = lightcone_positive(rec, rx, ry, rz) ? xo[s] : mo;
+                                xo[s] = inside_cone(s, rec) ? xo[s] : mo;
                             }
                             n -= half;
                         }
@@ -601,8 +641,8 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
                         const bool was_before = g == kBracketBefore;
                         const bool in_range = g >= 1 && g < D;
                         const int ga = in_range ? g : D - 1;  // 1 <= ga <= D - 1
-                        const bool fa = lightcone_positive(cur.rec(s * D + ga), rx, ry, rz);
-                        const bool fb = lightcone_positive(cur.rec(s * D + ga - 1), rx, ry, rz);
+                        const bool fa = inside_cone(s, cur.rec(s * D + ga));
+                        const bool fb = inside_cone(s, cur.rec(s * D + ga - 1));
                         hit[s] = was_before ? !fa : (in_range && fa && !fb);
                         // a bracket index leaves this block only if it is
                         // one (the entry of an excluded pair is never
@@ -613,7 +653,7 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
                     }
                     for (int s = 0; s < S; ++s) {
                         if (!hit[s] && valid[s]) {
-                            auto test = [&](int bb) { return lightcone_positive(cur.rec(s * D + bb), rx, ry, rz); };
+                            auto test = [&](int bb) { return inside_cone(s, cur.rec(s * D + bb)); };
                             const int g = kcur[s];
                             int fb = 0;
                             bk[s] = search_guided(test, D, g == kBracketBefore || g >= D ? (float)(D - 1) : (float)g, 6,
@@ -640,9 +680,8 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
                 for (int s = 0; s < S; ++s) {
                     int b = -1;
                     if (valid[s]) {
-                        auto test = [&](int bb) { return lightcone_positive(cur.rec(s * D + bb), rx, ry, rz); };
-                        const double4 wn = cur.rec(s * D);
-                        const float Rx = (float)(rx - wn.x), Ry = (float)(ry - wn.y), Rz = (float)(rz - wn.z);
+                        auto test = [&](int bb) { return inside_cone(s, cur.rec(s * D + bb)); };
+                        const float Rx = (float)d0x[s], Ry = (float)d0y[s], Rz = (float)d0z[s];
                         const float r2 = Rx * Rx + Ry * Ry + Rz * Rz;
                         float g;
                         if (GUESS == 1 || GUESS == 2) {
