@@ -90,7 +90,8 @@ typedef enum {
 
 typedef struct {
     int64_t n;             /* particles, >= 2                                */
-    int32_t depth;         /* history slots D, 2 <= D <= 4096                */
+    int32_t depth;         /* history slots D, 2 <= D <= 4064 (the deepest
+                              history whose LDS tile fits a CU)             */
     int32_t ext_field;     /* 0: none; 1: centred dipole, moment along +z    */
     double q;              /* charge of every macro-particle (C)             */
     double m;              /* mass of every macro-particle (kg), > 0         */

@@ -199,8 +199,8 @@ empp_status validate(const empp_config *c)
         return fail(EMPP_EINVAL, "n = %lld: need at least 2 particles", (long long)c->n);
     if (c->n > (int64_t)1 << 31)
         return fail(EMPP_EINVAL, "n = %lld exceeds 2^31", (long long)c->n);
-    if (c->depth < 2 || c->depth > 4096)
-        return fail(EMPP_EINVAL, "depth = %d: need 2 <= D <= 4096", c->depth);
+    if (c->depth < 2 || c->depth > kMaxDepth)
+        return fail(EMPP_EINVAL, "depth = %d: need 2 <= D <= %d", c->depth, kMaxDepth);
     if (!(c->dt > 0.0) || !std::isfinite(c->dt))
         return fail(EMPP_EINVAL, "dt must be positive and finite");
     if (!(c->m > 0.0) || !std::isfinite(c->m) || !std::isfinite(c->q))

@@ -21,6 +21,10 @@ constexpr int kBlock = EMPP_PAIR_BLOCK;  // threads per block of the mixed pair 
 #define EMPP_FP64_BLOCK 1024
 #endif
 constexpr int kBlockFp64 = EMPP_FP64_BLOCK;
+
+// Deepest supported history (slots): the pair kernel's LDS tile for it, one
+// history of 32-byte records plus its light distances, fills a CU's 160 KiB.
+constexpr int kMaxDepth = 4064;
 constexpr int kMaxSplits = 1024;   // source chunks of one launch
 
 // History layout in HBM (library-owned workspace):

@@ -44,7 +44,7 @@ constexpr int lockstep_sources(bool mix, int guess) { return mix && guess == 2 ?
 // staged tile fits in kHalfRecs records, else one sized to the tile
 // (depths above 2048; up to 4096 slots use the CU's 160 KiB with the slot
 // light distances).
-inline int pair_nbuf(int D, int tile) { return (int64_t)tile * D <= kHalfRecs ? 2 : 1; }
+constexpr int pair_nbuf(int D, int tile) { return (int64_t)tile * D <= kHalfRecs ? 2 : 1; }
 
 // Per-source data of the staged tiles, in 16-byte units: the straight-line
 // data of the guided searches (per buffer and source {beta, 1 - beta^2} and
@@ -52,7 +52,7 @@ inline int pair_nbuf(int D, int tile) { return (int64_t)tile * D <= kHalfRecs ? 
 // wavefront and source, and the newest samples w_n of three tiles' sources.
 constexpr int kLineRecs = 2 * 2 * 4 + 2 * (kBlockFp64 / 64) * 4 / 4 + 3 * 4 * 2;
 
-inline size_t pair_lds_bytes(int D, int tile)
+constexpr size_t pair_lds_bytes(int D, int tile)
 {
     const size_t half = pair_nbuf(D, tile) == 2 ? kHalfRecs : (size_t)tile * D;
     return (size_t)pair_nbuf(D, tile) * 2 * half * sizeof(double2) + (size_t)((D + 1) & ~1) * sizeof(double) +
@@ -61,7 +61,12 @@ inline size_t pair_lds_bytes(int D, int tile)
 
 // Sources per staged LDS tile for a history depth: as many as fill a
 // buffer of kHalfRecs records, at most four (one barrier per staged tile).
-inline int pair_staged_tile(int D) { return D <= kHalfRecs ? std::min(4, kHalfRecs / D) : 1; }
+constexpr int pair_staged_tile(int D) { return D <= kHalfRecs ? std::min(4, kHalfRecs / D) : 1; }
+
+// kMaxDepth is the deepest history a block's LDS (160 KiB per CU) holds:
+// one buffer of D records, the D light distances and the per-source data.
+static_assert(pair_lds_bytes(kMaxDepth, pair_staged_tile(kMaxDepth)) <= 160 * 1024, "LDS of the deepest history");
+static_assert(pair_lds_bytes(kMaxDepth + 2, pair_staged_tile(kMaxDepth + 2)) > 160 * 1024 - 64, "kMaxDepth is tight");
 
 namespace {
 

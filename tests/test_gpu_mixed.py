@@ -28,7 +28,7 @@ def orc():
 
 
 @pytest.mark.parametrize("guess", [0, 2])
-@pytest.mark.parametrize("n,depth,m", [(48, 64, 300), (300, 128, 257)])
+@pytest.mark.parametrize("n,depth,m", [(48, 64, 300), (300, 128, 257), (24, 2500, 70)])
 def test_mixed_fields_at_wiggly(orc, n, depth, m, guess):
     print(f"case mixed wiggly n={n} D={depth} m={m} guess={guess}", flush=True)
     dt = 1e-13

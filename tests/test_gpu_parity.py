@@ -27,10 +27,14 @@ def orc():
 
 
 @pytest.mark.parametrize("guess", [0, 2])
-@pytest.mark.parametrize("n,depth,m", [(48, 64, 300), (61, 37, 129), (300, 128, 257)])
+@pytest.mark.parametrize("n,depth,m", [(48, 64, 300), (61, 37, 129), (300, 128, 257), (40, 600, 70), (40, 1500, 70),
+                                       (24, 2500, 70), (24, 4064, 70)])
 def test_fields_at_wiggly(orc, n, depth, m, guess):
     """Curving sources (non-zero acceleration in history), external
-    targets spanning several LDS tiles and ragged tails."""
+    targets spanning several LDS tiles and ragged tails.  The depths cover
+    every LDS layout: four, three and one source per double-buffered tile
+    (D <= 512, D = 600, 1024 < D <= 2048) and one buffer sized to the
+    history (D > 2048, up to the largest supported depth)."""
     print(f"case wiggly n={n} D={depth} m={m} guess={guess}", flush=True)
     dt = 1e-13
     T, w, v = bunch.wiggly_history(n, depth, dt, beta=0.9, accel_rel=0.1, seed=n + depth)
