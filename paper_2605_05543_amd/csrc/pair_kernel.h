@@ -3,13 +3,14 @@
 //
 // One thread owns one target.  A block of kBlockFp64 (1024) targets walks its
 // chunk of sources in staged tiles of up to four sources: the tile's
-// histories (positions plus the light distance c (t - T_k) of every slot)
+// histories, as the per-sample part of the split light-cone test (offsets
+// from each source's newest sample and L^2 - |offset|^2, see pair_common.h),
 // are staged once into LDS, double-buffered behind one barrier per tile, and
 // every target of the block then searches them, so each history byte read
 // from L2/HBM serves 1024 targets.  The sources of a tile are searched in
 // groups of S in lockstep (a fixed number of bisection steps, no divergence);
-// then the 2 S bracket velocity records are fetched together and the S pair
-// fields evaluated.  Targets are visited in a spatial (Morton) order so that
+// then, source by source, the two bracket velocity records are fetched and
+// the pair field evaluated.  Targets are visited in a spatial (Morton) order so that
 // the lanes of a wavefront probe nearby history slots.  Sums are kept per
 // target in registers: a plain partial merged into a compensated total
 // (Neumaier in FP64 every 16 sources, Knuth's two-sum in FP32 every 4);
@@ -42,8 +43,8 @@ constexpr int lockstep_sources(bool mix, int guess) { return mix && guess == 2 ?
 
 // LDS buffers: two of 64 KiB (staging overlapped with the search) while a
 // staged tile fits in kHalfRecs records, else one sized to the tile
-// (depths above 2048; up to 4096 slots use the CU's 160 KiB with the slot
-// light distances).
+// (depths above 2048; kMaxDepth slots fill the CU's 160 KiB with the slot
+// light distances and the per-source data).
 constexpr int pair_nbuf(int D, int tile) { return (int64_t)tile * D <= kHalfRecs ? 2 : 1; }
 
 // Per-source data of the staged tiles, in 16-byte units: the straight-line
@@ -63,10 +64,8 @@ constexpr size_t pair_lds_bytes(int D, int tile)
 // buffer of kHalfRecs records, at most four (one barrier per staged tile).
 constexpr int pair_staged_tile(int D) { return D <= kHalfRecs ? std::min(4, kHalfRecs / D) : 1; }
 
-// kMaxDepth is the deepest history a block's LDS (160 KiB per CU) holds:
-// one buffer of D records, the D light distances and the per-source data.
-static_assert(pair_lds_bytes(kMaxDepth, pair_staged_tile(kMaxDepth)) <= 160 * 1024, "LDS of the deepest history");
-static_assert(pair_lds_bytes(kMaxDepth + 2, pair_staged_tile(kMaxDepth + 2)) > 160 * 1024 - 64, "kMaxDepth is tight");
+static_assert(pair_lds_bytes(kMaxDepth, pair_staged_tile(kMaxDepth)) <= 160 * 1024,
+              "the deepest history's tile, light distances and per-source data fit a CU's LDS");
 
 namespace {
 
