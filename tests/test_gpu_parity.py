@@ -280,3 +280,20 @@ def test_c3_size_accelerating_history(orc):
     print(f"   before-history fraction {float((k0 < 0).mean()):.3f}", flush=True)
     assert_kstar("C3 accelerating", k, k0)
     assert_fields("C3 accelerating (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
+
+
+@pytest.mark.parametrize("splits", [48, 7, 1])
+def test_source_chunks_of_any_size(orc, splits):
+    """Source chunks from one source each (a chunk shorter than a staged
+    tile) to one chunk of all sources: k* and fields against the oracle."""
+    print(f"case source chunks: {splits} chunks of 48 sources", flush=True)
+    n, depth, m, dt = 48, 64, 100, 1e-13
+    T, w, v = bunch.wiggly_history(n, depth, dt, beta=0.9, accel_rel=0.1, seed=77)
+    rng = np.random.default_rng(78)
+    x = 1.5e-3 * rng.standard_normal((3, m))
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], x, want_kstar=True, want_abs=True)
+    with _ctx(n, depth, dt, source_splits=splits) as ctx:
+        ctx.set_history(T, w, v, np.zeros((3, n)))
+        E, B, k = ctx.fields_at(T[-1], x, want_kstar=True)
+    assert_kstar("chunks", k, k0)
+    assert_fields("chunks", E, B, E0, B0, SE, SB)
