@@ -1,0 +1,59 @@
+"""Write c5_subset.json: the oracle's self-fields and bracket checksums at 1024
+seeded targets of the full-scale workload (N = 262144 electrons, D = 1024
+slots, 5 MeV bunch at 3 R_E in the dipole, straight-line prior history), the
+reference for the GPU's FP64 and mixed-precision passes at that size.
+
+Only the oracle computes these values (test infrastructure).  The file
+records the sha256 of the oracle's C source it was made with; a CPU test
+flags the file as stale when that source changes.  Run from the repository
+root (about 25 minutes on 8 cores, 14 GB of memory):
+
+    python tests/golden/make_c5_subset.py
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+
+import oracle  # noqa: E402
+from paper_2605_05543_amd import bunch  # noqa: E402
+from parity import bracket_checksums  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c5_subset.json")
+TARGETS, SEED = 1024, 106
+
+
+def oracle_source_sha():
+    return hashlib.sha256(open(os.path.join(ROOT, "oracle", "empp_oracle.c"), "rb").read()).hexdigest()
+
+
+def main():
+    wl = bunch.C5
+    n = wl.bunch.n
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    sub = bunch.target_subset(n, TARGETS, SEED)
+    orc = oracle.get()
+    t0 = time.time()
+    T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
+    E, B, k, SE, SB = orc.fields(T, w, v, -bunch.E_CHARGE, T[-1], r[:, sub], sub, want_kstar=True, want_abs=True)
+    s1, s2 = bracket_checksums(k)
+    doc = {
+        "what": "oracle self-fields at seeded targets of the N=262144, D=1024 workload; see make_c5_subset.py",
+        "oracle_sha256": oracle_source_sha(),
+        "targets": sub.tolist(),
+        "E": E.tolist(), "B": B.tolist(), "SE": SE.tolist(), "SB": SB.tolist(),
+        "kstar_sum": s1.tolist(), "kstar_weighted_sum": s2.tolist(),
+        "before_history_fraction": float((k < 0).mean()),
+    }
+    with open(OUT, "w") as f:
+        json.dump(doc, f)
+    print(f"wrote {OUT} in {time.time() - t0:.0f} s")
+
+
+if __name__ == "__main__":
+    main()

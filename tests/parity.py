@@ -50,3 +50,25 @@ def assert_mixed(tag, got_E, got_B, ref_E, ref_B, SE, SB, tol=MIXED_TOL):
     out = mixed_report(tag, got_E, got_B, ref_E, ref_B, SE, SB)
     assert out["E"]["max_over_rms"] <= tol and out["B"]["max_over_rms"] <= tol, out
     return out
+
+
+def bracket_checksums(kstar):
+    """Per target of a [m, N] k* array: sum_j (k*_aj + 2) and
+    sum_j (j + 1)(k*_aj + 2), exact in int64 (a wrong bracket on any one
+    pair changes the second sum)."""
+    k = np.asarray(kstar).astype(np.int64) + 2
+    j = np.arange(1, k.shape[1] + 1, dtype=np.int64)
+    return k.sum(axis=1), (k * j).sum(axis=1)
+
+
+def load_c5_subset():
+    """The stored oracle reference at 1024 targets of the N=262144, D=1024
+    workload (written by tests/golden/make_c5_subset.py)."""
+    import json
+    import os
+
+    doc = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_subset.json")))
+    out = {k: np.asarray(doc[k]) for k in ("targets", "E", "B", "SE", "SB", "kstar_sum", "kstar_weighted_sum")}
+    out["targets"] = out["targets"].astype(np.int64)
+    out["before_history_fraction"] = doc["before_history_fraction"]
+    return out

@@ -87,3 +87,33 @@ def test_beam_rotation():
     assert abs(d1 / d0 - 1) < 2e-5  # coordinates of 3 R_E round to 3.7 nm
     mean_dir = ul.mean(axis=1) / np.linalg.norm(ul.mean(axis=1))
     assert mean_dir @ (R @ [0, 0, 1]) > 0.999
+
+
+def test_c5_subset_fixture_is_current():
+    """The stored full-scale reference (oracle fields at 1024 seeded targets
+    of the N=262144, D=1024 workload) was written by the current oracle
+    source, for the targets the seeded generator draws today, and its
+    bracket checksums lie in the range the history depth allows."""
+    import hashlib
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    doc = json.load(open(os.path.join(root, "tests", "golden", "c5_subset.json")))
+    sha = hashlib.sha256(open(os.path.join(root, "oracle", "empp_oracle.c"), "rb").read()).hexdigest()
+    assert doc["oracle_sha256"] == sha, "oracle changed: rerun tests/golden/make_c5_subset.py"
+    n, depth = bunch.C5.bunch.n, bunch.C5.depth
+    sub = bunch.target_subset(n, 1024, 106)
+    assert doc["targets"] == sub.tolist()
+    for key in ("E", "B"):
+        a = np.asarray(doc[key])
+        assert a.shape == (3, 1024) and np.all(np.isfinite(a))
+    for key in ("SE", "SB"):
+        a = np.asarray(doc[key])
+        assert a.shape == (1024,) and np.all(a > 0)
+    # |field| <= sum of magnitudes, target by target
+    assert np.all(np.linalg.norm(doc["E"], axis=0) <= np.asarray(doc["SE"]) * (1 + 1e-12))
+    # k* is -1 (before the history), 0 (self pair) or 1..D-1, so per pair
+    # k* + 2 lies in [1, D + 1]; the self pair contributes exactly 2
+    s1 = np.asarray(doc["kstar_sum"], dtype=np.int64)
+    s2 = np.asarray(doc["kstar_weighted_sum"], dtype=np.int64)
+    assert np.all(s1 >= n + 1) and np.all(s1 <= n * (depth + 1))
+    assert np.all(s2 >= n * (n + 1) // 2) and np.all(s2 <= (depth + 1) * n * (n + 1) // 2)

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_2605_05543_amd import bunch
-from parity import assert_kstar, assert_mixed
+from parity import assert_kstar, assert_mixed, bracket_checksums, load_c5_subset
 
 pytestmark = pytest.mark.gpu
 
@@ -88,26 +88,26 @@ def test_mixed_c3_full_size_sampled(orc, guess):
     assert_mixed("mixed C3 (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
 
 
-def test_mixed_c5_full_size_sampled(orc):
+def test_mixed_c5_full_size_subset():
     """C5 size (N=262144, D=1024, 5 MeV: gamma = 10.8, so forward pairs have
-    1 - eta_hat.beta down to 0.004): the mixed step's fields at 256 seeded
-    targets against the oracle, and their k*."""
+    1 - eta_hat.beta down to 0.004): the mixed step's fields at 1024 seeded
+    targets against the stored oracle values, and the bracket checksums."""
     wl = bunch.C5
-    print("case mixed C5 sampled", flush=True)
+    print("case mixed C5, 1024 stored targets", flush=True)
+    ref = load_c5_subset()
     r, u = bunch.gaussian_bunch(wl.bunch)
     n = wl.bunch.n
-    sub = bunch.target_subset(n, 256, 105)
-    T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
-    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], r[:, sub], sub, want_kstar=True, want_abs=True)
-    del w, v
+    sub = ref["targets"]
     with _ctx(n, wl.depth, wl.dt, guess=2, ext_field=1, dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re) as ctx:
         ctx.init_bunch(r, u, 0.0)
         ctx.init_history_straight()
         _, _, k = ctx.fields_at(0.0, r[:, sub], sub, want_kstar=True)
         ctx.step(1)
         Es, Bs = ctx.fields()
-    assert_kstar("mixed C5", k, k0)
-    assert_mixed("mixed C5 (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
+    s1, s2 = bracket_checksums(k)
+    assert np.array_equal(s1, ref["kstar_sum"]) and np.array_equal(s2, ref["kstar_weighted_sum"]), \
+        np.flatnonzero((s1 != ref["kstar_sum"]) | (s2 != ref["kstar_weighted_sum"]))[:5]
+    assert_mixed("mixed C5 (step launch)", Es[:, sub], Bs[:, sub], ref["E"], ref["B"], ref["SE"], ref["SB"])
 
 
 def test_mixed_c1_free_running_position_error(orc):
