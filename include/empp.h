@@ -73,7 +73,10 @@ typedef enum {
 typedef enum {
     EMPP_GUESS_BISECT = 0,    /* the paper's search: oldest-sample test, then
                                  bisection of the whole history            */
-    EMPP_GUESS_MLP = 1,       /* start from the surrogate network's delay  */
+    EMPP_GUESS_MLP = 1,       /* start from the surrogate network's delay
+                                 (modes 1 and 3 need depth >= 5: the
+                                 network reads the slot 4 steps back;
+                                 EUNSUPPORTED otherwise)                    */
     EMPP_GUESS_BALLISTIC = 2, /* start from the closed-form delay of a source
                                  coasting with its newest velocity          */
     EMPP_GUESS_MLP_PAIR = 3,  /* surrogate evaluated for every pair (fields_at

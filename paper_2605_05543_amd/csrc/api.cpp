@@ -221,6 +221,9 @@ empp_status validate(const empp_config *c)
         return fail(EMPP_EINVAL, "recon must be 0 (linear) or 1 (midpoint)");
     if (c->guess_group_log2 != 0 && (c->guess_group_log2 < 6 || c->guess_group_log2 > 16))
         return fail(EMPP_EINVAL, "guess_group_log2 must be 0 or 6..16");
+    // the network's history-slope input reads the slot four steps back
+    if ((c->guess == EMPP_GUESS_MLP || c->guess == EMPP_GUESS_MLP_PAIR) && c->depth < 5)
+        return fail(EMPP_EUNSUPPORTED, "the surrogate guess needs at least 5 history slots");
     if (c->recon == 1 && (c->precision != EMPP_FP64 || c->guess != EMPP_GUESS_BISECT || c->adaptive))
         return fail(EMPP_EUNSUPPORTED, "the midpoint ablation runs on the FP64 path with bisection and a fixed step");
     if (c->adaptive) {

@@ -48,7 +48,7 @@ def test_workspace_size_and_validation():
     assert ring + 65536 * 65536 * 2 <= warm < nbytes + 65536 * 65536 * 2
     for bad in (dict(n=1), dict(depth=1), dict(depth=4065), dict(dt=0.0), dict(dt=float("nan")), dict(m=-1.0),
                 dict(ext_field=3), dict(precision=7), dict(guess=9), dict(guess_group_log2=5),
-                dict(guess_group_log2=17), dict(recon=2)):
+                dict(guess_group_log2=17), dict(recon=2), dict(guess=1, depth=4), dict(guess=3, depth=2)):
         c = _lib.Config(n=64, depth=32, q=-1.0, m=1.0, dt=1e-13)
         for k, v in bad.items():
             setattr(c, k, v)

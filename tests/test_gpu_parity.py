@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 from paper_2605_05543_amd import bunch
-from parity import assert_fields, assert_kstar, bracket_checksums, load_c5_subset
+from parity import assert_fields, assert_kstar, assert_mixed, bracket_checksums, load_c5_subset
 
 pytestmark = pytest.mark.gpu
 
@@ -299,3 +299,31 @@ def test_source_chunks_of_any_size(orc, splits):
         E, B, k = ctx.fields_at(T[-1], x, want_kstar=True)
     assert_kstar("chunks", k, k0)
     assert_fields("chunks", E, B, E0, B0, SE, SB)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_smallest_and_empty_inputs(orc, precision):
+    """The smallest sizes the method allows: two or three sources, a history
+    of two or three slots (one or two segments), one target, more targets
+    than sources (chunked), and no targets at all.  Targets sit microns
+    from source 0, so its pairs fall inside the short history while the
+    millimetre-distant sources' pairs fall before it."""
+    for n, depth, m in ((2, 2, 5), (2, 3, 3), (3, 2, 1)):
+        print(f"case smallest inputs n={n} D={depth} m={m} precision={precision}", flush=True)
+        dt = 1e-13
+        T, w, v = bunch.wiggly_history(n, depth, dt, beta=0.9, accel_rel=0.1, seed=11 + n + depth)
+        rng = np.random.default_rng(12 + m)
+        x = w[-1][:, :1] + 4e-6 * rng.standard_normal((3, m))
+        g = 1 / np.sqrt(1 - (v[-1] ** 2).sum(0) / bunch.C_LIGHT**2)
+        E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], x, want_kstar=True, want_abs=True)
+        assert (k0 > 0).any() and (k0 < 0).any()
+        with _ctx(n, depth, dt, precision=precision) as ctx:
+            ctx.set_history(T, w, v, v[-1] * g)
+            E, B, k = ctx.fields_at(T[-1], x, want_kstar=True)
+            Ee, Be = ctx.fields_at(T[-1], np.zeros((3, 0)))
+        assert Ee.shape == (3, 0) and Be.shape == (3, 0)
+        assert_kstar("smallest", k, k0)
+        if precision == 0:
+            assert_fields("smallest", E, B, E0, B0, SE, SB)
+        else:
+            assert_mixed("smallest (mixed)", E, B, E0, B0, SE, SB)
