@@ -319,8 +319,12 @@ empp_status empp_transport(empp_ctx *ctx, double dt_max, double gyro_fraction, i
  * Stage-II positions; proper velocities, slot times, the spatial order,
  * step counters and clock) to a binary file at path, and read it back into
  * a context created with the same n, depth, q, m and dt (EINVAL
- * otherwise, or on an unreadable or truncated file, after which the
- * context holds no state).  Caches (warm-start brackets, surrogate
+ * otherwise, or on an unreadable or truncated file or a spatial order that
+ * is not a permutation of 0..n-1, after which the context holds no
+ * state).  Layout: an 88-byte header (magic "EMPPCKP1", n, depth, head,
+ * step counters, clock, stage, q, m, dt), then T[depth], u[3][n] and the
+ * order int32[n], then the two rings (Stage I) or the positions, step
+ * keys and clock (Stage II).  Caches (warm-start brackets, surrogate
  * guesses) and the last step's fields are not saved.                     */
 empp_status empp_save(empp_ctx *ctx, const char *path);
 empp_status empp_load(empp_ctx *ctx, const char *path);

@@ -1542,6 +1542,26 @@ empp_status file_to_dev(empp_ctx *ctx, FILE *f, void *dev, uint64_t bytes)
     }
     return EMPP_OK;
 }
+
+// The target order indexes the history ring in the pair kernel: accept it
+// only as a permutation of 0..N-1.
+empp_status order_from_file(empp_ctx *ctx, FILE *f)
+{
+    const int64_t N = ctx->cfg.n;
+    std::vector<int32_t> ord((size_t)N);
+    if (fread(ord.data(), sizeof(int32_t), (size_t)N, f) != (size_t)N)
+        return fail(EMPP_EINVAL, "checkpoint truncated");
+    std::vector<char> seen((size_t)N, 0);
+    for (int64_t i = 0; i < N; ++i) {
+        const int32_t k = ord[(size_t)i];
+        if (k < 0 || k >= N || seen[(size_t)k])
+            return fail(EMPP_EINVAL, "corrupt checkpoint: target order is not a permutation");
+        seen[(size_t)k] = 1;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->order(), ord.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return EMPP_OK;
+}
 }  // namespace
 
 empp_status empp_save(empp_ctx *ctx, const char *path)
@@ -1621,7 +1641,7 @@ empp_status empp_load(empp_ctx *ctx, const char *path)
     if (st == EMPP_OK)
         st = file_to_dev(ctx, f, ctx->u(), 3 * N * sizeof(double));
     if (st == EMPP_OK)
-        st = file_to_dev(ctx, f, ctx->order(), N * sizeof(int32_t));
+        st = order_from_file(ctx, f);
     if (st == EMPP_OK && h.stage == 1) {
         st = file_to_dev(ctx, f, ctx->ring_w(), (uint64_t)N * D * sizeof(double4));
         if (st == EMPP_OK)

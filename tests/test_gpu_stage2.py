@@ -205,3 +205,21 @@ def test_load_rejects_mismatch(tmp_path):
         with pytest.raises(EmppError) as ei:
             c.load(bad)
         assert ei.value.status == EMPP_EINVAL
+    # a spatial order that is not a permutation (it indexes the ring) and a
+    # truncated file are refused before anything runs on them
+    raw = bytearray(open(path, "rb").read())
+    at = 88 + 8 * 8 + 3 * 16 * 8  # header, T[8], u[3][16]
+    for name, data in (("dup", raw[:at] + raw[at + 4:at + 8] + raw[at + 4:]),
+                       ("range", raw[:at] + (16).to_bytes(4, "little") + raw[at + 4:]),
+                       ("short", raw[:len(raw) - 8])):
+        p2 = str(tmp_path / f"{name}.bin")
+        open(p2, "wb").write(bytes(data))
+        with _ctx(16, 8, 1e-13) as c:
+            with pytest.raises(EmppError) as ei:
+                c.load(p2)
+            assert ei.value.status == EMPP_EINVAL, name
+            with pytest.raises(EmppError) as ei:
+                c.step(1)
+            assert ei.value.status == EMPP_ESTATE
+    with _ctx(16, 8, 1e-13) as c:
+        c.load(path)  # the intact file still loads
