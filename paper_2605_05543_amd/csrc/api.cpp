@@ -777,18 +777,36 @@ empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
     return EMPP_OK;
 }
 
+// Device scratch of one call, freed on every return path once the stream
+// has drained.
+struct StreamScratch {
+    hipStream_t stream;
+    void *ptr = nullptr;
+    explicit StreamScratch(hipStream_t s) : stream(s) {}
+    StreamScratch(const StreamScratch &) = delete;
+    StreamScratch &operator=(const StreamScratch &) = delete;
+    ~StreamScratch()
+    {
+        if (ptr) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(ptr);
+        }
+    }
+};
+
 static empp_status fields_dev_impl(empp_ctx *ctx, int64_t m, const double *x_dev, const int64_t *self_dev,
                                    double *E_dev, double *B_dev, int32_t *kstar_dev)
 {
     const int64_t N = ctx->cfg.n;
     // targets go through in chunks of at most N (the partials buffer's size)
     for (int64_t a0 = 0; a0 < m; a0 += N) {
-        int64_t mc = std::min<int64_t>(N, m - a0);
+        const int64_t mc = std::min<int64_t>(N, m - a0);
+        StreamScratch xbuf(ctx->stream), obuf(ctx->stream), gbuf(ctx->stream);
         // x for the chunk must be a [3][mc] array: chunking needs a copy
         const double *xc = x_dev;
-        double *tmpx = nullptr;
         if (m > N) {
-            HIP_TRY(hipMalloc((void **)&tmpx, 3 * mc * sizeof(double)));
+            HIP_TRY(hipMalloc(&xbuf.ptr, 3 * mc * sizeof(double)));
+            double *tmpx = (double *)xbuf.ptr;
             for (int k = 0; k < 3; ++k)
                 HIP_TRY(hipMemcpyAsync(tmpx + k * mc, x_dev + k * m + a0, mc * sizeof(double),
                                        hipMemcpyDeviceToDevice, ctx->stream));
@@ -802,39 +820,26 @@ static empp_status fields_dev_impl(empp_ctx *ctx, int64_t m, const double *x_dev
         float *G_pair = nullptr;
         double3 *cent_pair = nullptr;
         if (ctx->cfg.guess == EMPP_GUESS_MLP_PAIR) {
-            HIP_TRY(hipMalloc((void **)&G_pair, (size_t)mc * N * sizeof(float) + (size_t)mc * sizeof(double3) + 256));
+            HIP_TRY(hipMalloc(&gbuf.ptr, (size_t)mc * N * sizeof(float) + (size_t)mc * sizeof(double3) + 256));
+            G_pair = (float *)gbuf.ptr;
             cent_pair = (double3 *)((char *)G_pair + align_up((size_t)mc * N * sizeof(float)));
         }
-        hipError_t e = launch_pair(ctx, p, kstar_dev != nullptr, G_pair, cent_pair);
-        if (G_pair) {
-            (void)hipStreamSynchronize(ctx->stream);
-            (void)hipFree(G_pair);
-        }
+        HIP_TRY(launch_pair(ctx, p, kstar_dev != nullptr, G_pair, cent_pair));
         double *Ec = E_dev, *Bc = B_dev;
-        double *tmpo = nullptr;
-        if (e == hipSuccess && m > N) {
-            e = hipMalloc((void **)&tmpo, 6 * mc * sizeof(double));
-            Ec = tmpo;
-            Bc = tmpo + 3 * mc;
+        if (m > N) {
+            HIP_TRY(hipMalloc(&obuf.ptr, 6 * mc * sizeof(double)));
+            Ec = (double *)obuf.ptr;
+            Bc = Ec + 3 * mc;
         }
-        if (e == hipSuccess)
-            e = launch_merge_fields(ctx->part(), ctx->nsplit, mc, Ec, Bc, ctx->stream);
-        if (e == hipSuccess && m > N) {
-            for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-                e = hipMemcpyAsync(E_dev + k * m + a0, Ec + k * mc, mc * sizeof(double), hipMemcpyDeviceToDevice,
-                                   ctx->stream);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(B_dev + k * m + a0, Bc + k * mc, mc * sizeof(double),
-                                       hipMemcpyDeviceToDevice, ctx->stream);
+        HIP_TRY(launch_merge_fields(ctx->part(), ctx->nsplit, mc, Ec, Bc, ctx->stream));
+        if (m > N) {
+            for (int k = 0; k < 3; ++k) {
+                HIP_TRY(hipMemcpyAsync(E_dev + k * m + a0, Ec + k * mc, mc * sizeof(double), hipMemcpyDeviceToDevice,
+                                       ctx->stream));
+                HIP_TRY(hipMemcpyAsync(B_dev + k * m + a0, Bc + k * mc, mc * sizeof(double), hipMemcpyDeviceToDevice,
+                                       ctx->stream));
             }
-            (void)hipStreamSynchronize(ctx->stream);
         }
-        if (tmpx)
-            (void)hipFree(tmpx);
-        if (tmpo)
-            (void)hipFree(tmpo);
-        if (e != hipSuccess)
-            return fail(EMPP_EDEVICE, "fields_at: %s", hipGetErrorString(e));
     }
     return EMPP_OK;
 }
