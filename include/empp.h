@@ -96,7 +96,8 @@ typedef struct {
     int32_t depth;         /* history slots D, 2 <= D <= 4064 (the deepest
                               history whose LDS tile fits a CU)             */
     int32_t ext_field;     /* 0: none; 1: centred dipole, moment along +z    */
-    double q;              /* charge of every macro-particle (C)             */
+    double q;              /* charge of every macro-particle (C); a weight w
+                              is q = -w e with m = w m_e (q/m unchanged)     */
     double m;              /* mass of every macro-particle (kg), > 0         */
     double dt;             /* fixed time step (s), > 0                       */
     double dipole_b0;      /* dipole equatorial field at radius dipole_re (T) */
