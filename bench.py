@@ -175,9 +175,19 @@ def cpu_baseline(wl, r, u, target_seconds=15.0):
     el = time.perf_counter() - t0
     value = m * (n - 1) / el
     log(f"  cpu oracle: {m} targets x {n - 1} sources in {el:.1f} s on {threads} threads: {value:.3e} pair-evals/s")
+    # the same scan on one thread, over a short sample (about 4 s)
+    m1 = int(max(2, min(n, 4.0 * value / threads / (n - 1))))
+    sub1 = bunch.target_subset(n, m1, 1003)
+    t0 = time.perf_counter()
+    orc.fields(T, w, v, -bunch.E_CHARGE, T[-1], r[:, sub1], sub1, nthreads=1)
+    el1 = time.perf_counter() - t0
+    value1 = m1 * (n - 1) / el1
+    log(f"  cpu oracle, one thread: {m1} targets in {el1:.1f} s: {value1:.3e} pair-evals/s")
     return {"value": value, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"fields at {m} seeded targets x {n - 1} sources, one step of {wl.name} "
-                      f"(FP64 C oracle, linear history scan), {el:.1f} s"}
+                      f"(FP64 C oracle, linear history scan), {el:.1f} s",
+            "single_core_value": value1,
+            "single_core_sample": f"{m1} seeded targets x {n - 1} sources on one thread, {el1:.1f} s"}
 
 
 def main():
