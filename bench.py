@@ -25,6 +25,9 @@ from paper_2605_05543_amd import bunch  # noqa: E402
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0  # dense matrix-core peak
+# one evaluation of the 10 -> 128 -> 128 -> 1 network: 2 x 17792 multiply-adds
+MLP_FLOP_EVAL = 2 * (10 * 128 + 128 * 128 + 128)
 
 # Algorithmic FP64 operations of one (target, source) pair, counted from the
 # method's steps (add, sub, mul = 1; sqrt, div = 1; compare = 0):
@@ -93,7 +96,9 @@ def train_surrogate(ctx, wl, r, epochs=2):
     ctx.step(4)
     ctx.surrogate_set(bunch.surrogate_init(0), bunch.sigma_ref_of(r))
     s3 = ctx.surrogate_samples_torch(half, seed=23)
-    rep = surrogate.train(ctx, [s2, s3], batch=8192, steps=epochs * (SURROGATE_SAMPLES // 8192))
+    batch = 8192
+    rep = surrogate.train(ctx, [s2, s3], batch=batch, steps=epochs * (SURROGATE_SAMPLES // batch))
+    rep["batch"] = batch
     del s2, s3
     log(f"  surrogate trained on {SURROGATE_SAMPLES:.1e} pairs: loss {rep['loss_first']:.3e} -> "
         f"{rep['loss_last']:.3e} in {rep['steps']} steps, {rep['seconds']:.2f} s")
@@ -148,8 +153,19 @@ def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_lo
         "rescues_per_pair": cnt["rescues"] / cnt["pairs"],
     }
     if guess == 1:
-        out["targets_per_guess"] = 1 << (group_log2 or 6)
+        # the network on the matrix cores: evaluations per launch x its BF16
+        # operations, over the measured guess-kernel time
+        tpg = 1 << (group_log2 or 6)
+        evals = -(-n // tpg) * n
+        out["targets_per_guess"] = tpg
+        if out["guess_kernel_ms"] > 0:
+            tf = evals * MLP_FLOP_EVAL / (out["guess_kernel_ms"] * 1e-3) / 1e12
+            out["guess_bf16_tflops"] = tf
+            out["guess_mfma_frac"] = tf / PEAK_BF16_TFLOPS
     if train_rep:
+        # forward plus input and weight gradients: about three forward passes
+        train_rep["bf16_tflops"] = (train_rep["steps"] * train_rep["batch"] * 3 * MLP_FLOP_EVAL
+                                    / train_rep["seconds"] / 1e12)
         out["surrogate_training"] = train_rep
     log(f"  {out['precision']}/{out['guess']}: {out['pair_evals_per_s']:.3e} pair-evals/s, "
         f"{out['ms_per_step']:.2f} ms/step, pair kernel {pair_ms:.2f} ms, {out['probes_per_pair']:.2f} probes/pair, "
