@@ -256,6 +256,7 @@ def main():
     n = wl.bunch.n
     launch_flops = plain["flops_per_pair"] * n * (n - 1)
     achieved = launch_flops / (plain["pair_kernel_ms"] * 1e-3) / 1e12
+    traffic = measured_traffic() if wl is bunch.C3 else None
     line = {
         "metric": "LW pair-evals/s at N=65536 (FP32+surrogate vs FP64 plain, <=1e-5 rel err)",
         "value": head["pair_evals_per_s"],
@@ -272,10 +273,12 @@ def main():
         "config": {"workload": wl.name, "n": n, "depth": wl.depth, "dt": wl.dt, "ext_field": wl.ext_field,
                    "precision": head["precision"], "search": head["guess"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-                     "traffic": measured_traffic() if wl is bunch.C3 else None,
+                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": traffic,
                      "kernel": "pair_fp64_kernel (plain FP64 path)",
-                     "flops_per_pair": plain["flops_per_pair"], "launch_ms": plain["pair_kernel_ms"]},
+                     "flops_per_pair": plain["flops_per_pair"], "launch_ms": plain["pair_kernel_ms"],
+                     # counted HBM bytes over the measured launch time, against 8 TB/s
+                     "hbm_gbs": traffic / (plain["pair_kernel_ms"] * 1e-3) / 1e9 if traffic else None,
+                     "hbm_frac": traffic / (plain["pair_kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS if traffic else None},
         "paths": results,
     }
     if not args.no_cpu:
