@@ -164,13 +164,14 @@ def test_c2_subset_and_invariants(orc):
 
 
 def test_c3_full_size_sampled(orc):
-    """C3 size (N=65536, D=512, dipole at 3 R_E): the step's fields at 128
-    seeded targets against the oracle, and k* of those targets."""
+    """C3 size (N=65536, D=512, dipole at 3 R_E): the step's fields at 1024
+    seeded targets against the oracle, and k* of those targets (6.7e7
+    pairs)."""
     wl = bunch.C3
-    print("case C3 full size sampled", flush=True)
+    print("case C3 full size sampled, 1024 targets", flush=True)
     r, u = bunch.gaussian_bunch(wl.bunch)
     n = wl.bunch.n
-    sub = bunch.target_subset(n, 128, 103)
+    sub = bunch.target_subset(n, 1024, 103)
     T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
     E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], r[:, sub], sub, want_kstar=True, want_abs=True)
     with _ctx(n, wl.depth, wl.dt, ext_field=1, dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re) as ctx:
