@@ -278,7 +278,8 @@ def main():
                      "flops_per_pair": plain["flops_per_pair"], "launch_ms": plain["pair_kernel_ms"],
                      # counted HBM bytes over the measured launch time, against 8 TB/s
                      "hbm_gbs": traffic / (plain["pair_kernel_ms"] * 1e-3) / 1e9 if traffic else None,
-                     "hbm_frac": traffic / (plain["pair_kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS if traffic else None},
+                     "hbm_frac": traffic / (plain["pair_kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS if traffic else None,
+                     "hbm_bytes_per_pair": traffic / (n * (n - 1)) if traffic else None},
         "paths": results,
     }
     if not args.no_cpu:
