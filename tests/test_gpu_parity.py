@@ -8,7 +8,8 @@ import pytest
 
 import oracle
 from paper_2605_05543_amd import bunch
-from parity import assert_fields, assert_kstar, assert_mixed, bracket_checksums, load_c5_subset
+from parity import (FP64_TOL, MIXED_TOL, assert_fields, assert_kstar, assert_mixed, bracket_checksums,
+                    field_errors, load_c5_subset)
 
 pytestmark = pytest.mark.gpu
 
@@ -328,3 +329,35 @@ def test_smallest_and_empty_inputs(orc, precision):
             assert_fields("smallest", E, B, E0, B0, SE, SB)
         else:
             assert_mixed("smallest (mixed)", E, B, E0, B0, SE, SB)
+
+
+def test_exact_tie_goes_older(orc):
+    """A sample exactly on the target's past light cone (light distance
+    2^-12 m, whose square is a double) belongs to the older side: k* = 9
+    for a tie 8 slots back, on the GPU as in the oracle, in both precisions
+    and with the bisection and the straight-line guess."""
+    from pins import _exact_light_delay
+
+    print("case exact tie", flush=True)
+    ns, dt = 16, 1e-13
+    r0 = np.array([[0.0, 1e-3], [0.0, 0.0], [0.0, 0.0]])
+    T, w, v = bunch.uniform_history(ns, dt, r0, np.zeros((3, 2)))
+    t = T[-1]
+    L0 = 2.0**-12
+    s = ns - 1 - 8
+    T[s] = t - _exact_light_delay(L0)
+    assert bunch.C_LIGHT * (t - T[s]) == L0
+    x = np.array([[L0], [0.0], [0.0]])
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, t, x, want_kstar=True, want_abs=True)
+    assert k0[0, 0] == 9
+    for precision in (0, 1):
+        for guess in (0, 2):
+            with _ctx(2, ns, dt, guess=guess, precision=precision) as ctx:
+                ctx.set_history(T, w, v, np.zeros((3, 2)))
+                E, B, k = ctx.fields_at(t, x, want_kstar=True)
+            assert_kstar(f"tie precision={precision} guess={guess}", k, k0)
+            # sources at rest on the target's axis: E along it, B exactly 0
+            e1, e2 = field_errors(E, E0, SE)
+            print(f"   E err/S {e1:.2e}, err/|E| {e2:.2e}; max |B| {np.abs(B).max():.1e}", flush=True)
+            assert e2 <= (FP64_TOL if precision == 0 else MIXED_TOL)
+            assert np.all(B == 0) and np.all(B0 == 0)
