@@ -280,6 +280,8 @@ def main():
                      "hbm_gbs": traffic / (plain["pair_kernel_ms"] * 1e-3) / 1e9 if traffic else None,
                      "hbm_frac": traffic / (plain["pair_kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS if traffic else None,
                      "hbm_bytes_per_pair": traffic / (n * (n - 1)) if traffic else None},
+        # the metric's comparison: FP32 + surrogate over the plain FP64 path
+        "speedup_vs_plain_fp64": head["pair_evals_per_s"] / plain["pair_evals_per_s"],
         "paths": results,
     }
     if not args.no_cpu:
