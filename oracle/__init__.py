@@ -61,6 +61,26 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+class Brackets(np.ndarray):
+    """The oracle's bracket index k* of every (target, source) pair (int32
+    [m, N]: slots back from the newest of the bracket's older end, -1 before
+    the history, 0 for an excluded pair), with ``alt``: the same array
+    except on near ties of the light-cone test, where it holds the bracket
+    the other decision gives.  Views and slices drop ``alt``."""
+
+    def __new__(cls, kstar, alt):
+        obj = np.asarray(kstar).view(cls)
+        obj.alt = alt
+        return obj
+
+    def __array_finalize__(self, obj):
+        self.alt = None
+
+    @property
+    def near_ties(self) -> int:
+        return 0 if self.alt is None else int(np.count_nonzero(self.alt != np.asarray(self)))
+
+
 class Oracle:
     """ctypes view of one compiled oracle library."""
 
@@ -70,9 +90,9 @@ class Oracle:
         self.path = path
         L = ctypes.CDLL(path)
         L.oracle_constants.argtypes = [_P]
-        L.oracle_retarded.argtypes = [_I64, _I32, _P, _P, _P, _D, _I64, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.oracle_retarded.argtypes = [_I64, _I32, _P, _P, _P, _D, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
         L.oracle_fields.argtypes = [_I64, _I32, _P, _P, _P, _D, _D, _I64, _P, _P, _P, _P, _P, ctypes.c_int, _P]
-        L.oracle_fields_abs.argtypes = [_I64, _I32, _P, _P, _P, _D, _D, _I64, _P, _P, _P, _P, _P, _P, _P,
+        L.oracle_fields_abs.argtypes = [_I64, _I32, _P, _P, _P, _D, _D, _I64, _P, _P, _P, _P, _P, _P, _P, _P,
                                         ctypes.c_int, _P]
         L.oracle_dipole.argtypes = [_D, _D, _I64, _P, _P]
         L.oracle_dipole.restype = None
@@ -110,16 +130,17 @@ class Oracle:
         m = x.shape[1]
         si = None if self_index is None else np.ascontiguousarray(self_index, dtype=np.int64)
         kstar = np.zeros((m, N), np.int32)
+        kalt = np.zeros((m, N), np.int32)
         dt_root = np.zeros((m, N))
         tr = np.zeros((m, N))
         wr = np.zeros((m, N, 3))
         vr = np.zeros((m, N, 3))
         ar = np.zeros((m, N, 3))
         st = self.L.oracle_retarded(N, ns, _ptr(T), _ptr(w), _ptr(v), float(t), m, _ptr(x), _ptr(si),
-                                    _ptr(kstar), _ptr(dt_root), _ptr(tr), _ptr(wr), _ptr(vr), _ptr(ar))
+                                    _ptr(kstar), _ptr(kalt), _ptr(dt_root), _ptr(tr), _ptr(wr), _ptr(vr), _ptr(ar))
         if st != OR_OK:
             raise OracleError(st)
-        return dict(kstar=kstar, dt_root=dt_root, tr=tr, wr=wr, vr=vr, ar=ar)
+        return dict(kstar=Brackets(kstar, kalt), kalt=kalt, dt_root=dt_root, tr=tr, wr=wr, vr=vr, ar=ar)
 
     # -- Sec. 2.1 fields ---------------------------------------------------------
     def fields(self, T, w, v, q, t, x, self_index=None, want_kstar=False, nthreads=None, want_abs=False):
@@ -130,17 +151,19 @@ class Oracle:
         E = np.zeros((3, m))
         B = np.zeros((3, m))
         kstar = np.zeros((m, N), np.int32) if want_kstar else None
+        kalt = np.zeros((m, N), np.int32) if want_kstar else None
         SE = np.zeros(m) if want_abs else None
         SB = np.zeros(m) if want_abs else None
         bad = np.full(2, -1, np.int64)
         nt = nthreads or self.max_threads()
         st = self.L.oracle_fields_abs(N, ns, _ptr(T), _ptr(w), _ptr(v), float(q), float(t), m, _ptr(x), _ptr(si),
-                                      _ptr(E), _ptr(B), _ptr(kstar), _ptr(SE), _ptr(SB), int(nt), _ptr(bad))
+                                      _ptr(E), _ptr(B), _ptr(kstar), _ptr(kalt), _ptr(SE), _ptr(SB), int(nt),
+                                      _ptr(bad))
         if st != OR_OK:
             raise OracleError(st, tuple(bad))
         out = (E, B)
         if want_kstar:
-            out = out + (kstar,)
+            out = out + (Brackets(kstar, kalt),)
         if want_abs:
             out = out + (SE, SB)
         return out

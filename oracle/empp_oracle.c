@@ -79,53 +79,66 @@ static void cross3(const double a[3], const double b[3], double out[3])
 static void neumaier_add(double *sum, double *comp, double x)
 {
     double t = *sum + x;
+#ifdef MUT_NEUMAIER_SIGN
+    if (fabs(*sum) >= fabs(x))
+        *comp -= (*sum - t) + x;
+    else
+        *comp -= (x - t) + *sum;
+#else
     if (fabs(*sum) >= fabs(x))
         *comp += (*sum - t) + x;
     else
         *comp += (x - t) + *sum;
+#endif
     *sum = t;
 }
 
 /* ---- Sec. 2.2: light-cone sign of a stored sample --------------------------
- * f_k = c (t - T_k) - |r - w_k|.  The bracket needs only its sign; it is
- * taken on squares so no square root enters the decision.  With the
- * source's newest sample w_n, the target's offset d0 = r - w_n and the
- * sample's offset D_k = w_n - w_k, |r - w_k|^2 = |d0|^2 + 2 d0.D_k + |D_k|^2,
- * so with L = c (t - T_k)
- *   f_k > 0  <=>  A_k - 2 d0.D_k > |d0|^2,   A_k = L^2 - |D_k|^2.
- * A_k belongs to the sample alone and |d0|^2 to the pair alone.  Fixed
- * evaluation (C99 fma, one rounding each, the build forbids other
- * contraction): A = L*L, then the squares of D_x, D_y, D_z taken off by
- * fma in that order; q = A, then d0_x (-2 D_x), d0_y (-2 D_y), d0_z (-2 D_z)
- * added by fma; R = d0_x d0_x, then d0_y d0_y and d0_z d0_z added by fma;
- * the sample is inside the past light cone when q > R.  The GPU path
- * evaluates the same expression and reproduces the decision bit for bit.   */
-static double offset_sq(const double d0[3])
-{
-    double R = d0[0] * d0[0];
-    R = fma(d0[1], d0[1], R);
-    return fma(d0[2], d0[2], R);
-}
+ * f_k = c (t - T_k) - |r - w_k|.  Only its sign is needed, and both terms are
+ * non-negative, so it is taken on squares: f_k > 0 <=> L^2 > |d|^2 with
+ * L = c (t - T_k) and d = r - w_k.  Plain evaluation in the written order,
+ * no fusion (the build forbids contraction):
+ *     LL = L * L,   dd = (d_x d_x + d_y d_y) + d_z d_z,   positive: LL > dd.
+ * An exact tie (LL == dd) goes to the older side, as the paper's bisection
+ * sends c dt <= |r - w(t_m)| to the older half.
+ *
+ * Rounding.  On the stored doubles (t, T_k, r, w_k) the exact value is
+ * F = L^2 - |d|^2.  L carries two roundings (the subtraction and the product
+ * with c) and LL one more; each d_c^2 carries two and the sum two more, so
+ * |(LL - dd) - F| <= gamma_5 (L^2 + |d|^2) with gamma_5 ~ 5 u, u = 2^-53.
+ * Hence LL - dd has the sign of F whenever |LL - dd| > 2^-50 (LL + dd): the
+ * decision is certified there.  Decisions with |LL - dd| <= NEAR_TIE (LL + dd),
+ * NEAR_TIE = 2^-44, are reported as near ties: the band is 64 times the
+ * certified bound, wide enough that any other FP64 evaluation order of the
+ * same test may decide them either way, and every consumer of the bracket
+ * accepts either neighbouring bracket there.                                */
+#define NEAR_TIE 0x1p-44
 
-static int lightcone_positive(const double d0[3], double R0sq, const double wn[3], const double wk[3],
-                              double t, double Tk)
+typedef struct {
+    int positive; /* decided f_k > 0                                    */
+    int near;     /* |LL - dd| within the near-tie band                  */
+} lc_sign_t;
+
+static lc_sign_t lightcone_sign(const double r[3], const double wk[3], double t, double Tk)
 {
     double L = C_LIGHT * (t - Tk);
-    double Dx = wn[0] - wk[0];
-    double Dy = wn[1] - wk[1];
-    double Dz = wn[2] - wk[2];
-    double A = L * L;
-    A = fma(-Dx, Dx, A);
-    A = fma(-Dy, Dy, A);
-    A = fma(-Dz, Dz, A);
-    double q = fma(d0[0], -2.0 * Dx, A);
-    q = fma(d0[1], -2.0 * Dy, q);
-    q = fma(d0[2], -2.0 * Dz, q);
+    double dx = r[0] - wk[0];
+    double dy = r[1] - wk[1];
+    double dz = r[2] - wk[2];
+    double LL = L * L;
+    double dd = (dx * dx + dy * dy) + dz * dz;
+    lc_sign_t s;
 #ifdef MUT_TIE_NEWER
-    return q >= R0sq;
+    s.positive = LL >= dd;
 #else
-    return q > R0sq;
+    s.positive = LL > dd;
 #endif
+#ifdef MUT_NO_NEAR_TIE
+    s.near = LL == dd;
+#else
+    s.near = fabs(LL - dd) <= NEAR_TIE * (LL + dd);
+#endif
+    return s;
 }
 
 static void load_sample(const double *a, int64_t N, int32_t s, int64_t j, double out[3])
@@ -152,6 +165,9 @@ typedef struct {
     double vr[3];     /* v(t_r)                                             */
     double ar[3];     /* a(t_r)                                             */
     double eta[3];    /* r - w(t_r), formed as (r - w_1) - v_1 dt           */
+    int near_tie;     /* 1: a sign decision of the scan was a near tie      */
+    int32_t alt_slot; /* near tie: the bracket the other decision gives
+                         (logical slot, -1 before the history)             */
 } retarded_t;
 
 /* Sec. 2.2 retarded-time determination for target position r at time t
@@ -168,6 +184,12 @@ typedef struct {
  * newest sample backwards.  If no stored sample has f_k > 0 the retarded
  * time precedes the history (t_r < t_0) and the oldest sample is used
  * with the extrapolation of Eq. (linear2).
+ *
+ * Near ties (see lightcone_sign).  When a decision of the scan falls in
+ * the near-tie band the pair is flagged and alt_slot names the bracket of
+ * the other decision: the flagged sample itself if it was decided outside
+ * the cone, the next older sample (or the before-history branch) if it was
+ * decided inside.
  *
  * Root.  With t_1, w_1, v_1 the bracket's left sample the linear
  * reconstruction w(t_r) ~ w_1 + v_1 delta t turns the retardation
@@ -188,14 +210,17 @@ static int solve_retarded(int64_t N, int32_t ns, const double *T, const double *
                           retarded_t *out)
 {
     int32_t ks = -1;
-    double wn[3];
-    load_sample(w, N, ns - 1, j, wn);
-    const double d0[3] = {r[0] - wn[0], r[1] - wn[1], r[2] - wn[2]};
-    const double R0sq = offset_sq(d0);
+    int near = 0;
+    int32_t alt = -1;
     for (int32_t s = ns - 2; s >= 0; --s) {
         double wk[3];
         load_sample(w, N, s, j, wk);
-        if (lightcone_positive(d0, R0sq, wn, wk, t, T[s])) {
+        lc_sign_t g = lightcone_sign(r, wk, t, T[s]);
+        if (g.near && !near) {
+            near = 1;
+            alt = g.positive ? s - 1 : s;
+        }
+        if (g.positive) {
             ks = s;
             break;
         }
@@ -236,6 +261,8 @@ static int solve_retarded(int64_t N, int32_t ns, const double *T, const double *
 
     out->slot = s1;
     out->before = before;
+    out->near_tie = near;
+    out->alt_slot = alt;
     out->dt_root = dtr;
     out->tr = T[s1] + dtr;
     /* eta = r - w(t_r) with w(t_r) = w_1 + v_1 dt.  It is formed as
@@ -340,13 +367,17 @@ static int lw_field(const double r[3], const retarded_t *rt, double q, double E[
     return OR_OK;
 }
 
+/* A bracket as slots back from the newest (1..ns-1), -1 before the history. */
+static int32_t back_offset(int32_t ns, int32_t slot) { return slot < 0 ? -1 : (ns - 1) - slot; }
+
 /* Per-pair inspection: retarded quantities for every (target, source).
  * Arrays [m][N] (scalars) or [m][N][3] (vectors); kstar as documented
- * above.  Pairs with j == self_index[a] are skipped (kstar 0).            */
+ * above, kalt the same except on near ties, where it holds the bracket of
+ * the other decision.  Pairs with j == self_index[a] are skipped (0).    */
 int oracle_retarded(int64_t N, int32_t ns, const double *T, const double *w, const double *v,
                     double t, int64_t m, const double *x, const int64_t *self_index,
-                    int32_t *kstar, double *dt_root, double *tr, double *wr, double *vr,
-                    double *ar)
+                    int32_t *kstar, int32_t *kalt, double *dt_root, double *tr, double *wr,
+                    double *vr, double *ar)
 {
     if (N < 1 || ns < 2 || m < 0)
         return OR_EINVAL;
@@ -356,13 +387,15 @@ int oracle_retarded(int64_t N, int32_t ns, const double *T, const double *w, con
             int64_t p = a * N + j;
             if (self_index && self_index[a] == j) {
                 if (kstar) kstar[p] = 0;
+                if (kalt) kalt[p] = 0;
                 continue;
             }
             retarded_t rt;
             int st = solve_retarded(N, ns, T, w, v, j, r, t, &rt);
             if (st != OR_OK)
                 return st;
-            if (kstar) kstar[p] = rt.before ? -1 : (ns - 1) - rt.slot;
+            if (kstar) kstar[p] = back_offset(ns, rt.before ? -1 : rt.slot);
+            if (kalt) kalt[p] = back_offset(ns, rt.near_tie ? rt.alt_slot : (rt.before ? -1 : rt.slot));
             if (dt_root) dt_root[p] = rt.dt_root;
             if (tr) tr[p] = rt.tr;
             for (int c = 0; c < 3; ++c) {
@@ -377,8 +410,8 @@ int oracle_retarded(int64_t N, int32_t ns, const double *T, const double *w, con
 
 int oracle_fields_abs(int64_t N, int32_t ns, const double *T, const double *w, const double *v,
                       double q, double t, int64_t m, const double *x, const int64_t *self_index,
-                      double *E, double *B, int32_t *kstar, double *SE, double *SB, int nthreads,
-                      int64_t *bad);
+                      double *E, double *B, int32_t *kstar, int32_t *kalt, double *SE, double *SB,
+                      int nthreads, int64_t *bad);
 
 /* Sec. 2.1 superposition: E_i = sum_{j != i} E_ij and the same for B,
  * each sum Neumaier-compensated over j in index order.  q is the charge
@@ -389,17 +422,17 @@ int oracle_fields(int64_t N, int32_t ns, const double *T, const double *w, const
                   double q, double t, int64_t m, const double *x, const int64_t *self_index,
                   double *E, double *B, int32_t *kstar, int nthreads, int64_t *bad)
 {
-    return oracle_fields_abs(N, ns, T, w, v, q, t, m, x, self_index, E, B, kstar, NULL, NULL,
+    return oracle_fields_abs(N, ns, T, w, v, q, t, m, x, self_index, E, B, kstar, NULL, NULL, NULL,
                              nthreads, bad);
 }
 
 /* As oracle_fields, and also S_E[a] = sum_j |E_aj|, S_B[a] = sum_j |B_aj|
  * (either may be NULL): the scale against which a sum's rounding error
- * is judged.                                                            */
+ * is judged; kalt (or NULL) as in oracle_retarded.                      */
 int oracle_fields_abs(int64_t N, int32_t ns, const double *T, const double *w, const double *v,
                       double q, double t, int64_t m, const double *x, const int64_t *self_index,
-                      double *E, double *B, int32_t *kstar, double *SE, double *SB, int nthreads,
-                      int64_t *bad)
+                      double *E, double *B, int32_t *kstar, int32_t *kalt, double *SE, double *SB,
+                      int nthreads, int64_t *bad)
 {
     if (N < 1 || ns < 2 || m < 0 || !T || !w || !v || !x || !E || !B)
         return OR_EINVAL;
@@ -417,11 +450,18 @@ int oracle_fields_abs(int64_t N, int32_t ns, const double *T, const double *w, c
         double aE = 0.0, aB = 0.0;
         int st = OR_OK;
         int64_t jfail = -1;
+#ifdef MUT_SUM_SKIP_LAST
+        for (int64_t j = 0; j < N - 1; ++j) {
+#else
         for (int64_t j = 0; j < N; ++j) {
+#endif
+#ifndef MUT_SELF_INDEX_IGNORED
             if (self_index && self_index[a] == j) {
                 if (kstar) kstar[a * N + j] = 0;
+                if (kalt) kalt[a * N + j] = 0;
                 continue;
             }
+#endif
             /* A target on a source's present position has eta = 0 at
              * t_r = t: the field is undefined (Sec. 2.1 divides by eta). */
             double wn[3];
@@ -441,7 +481,9 @@ int oracle_fields_abs(int64_t N, int32_t ns, const double *T, const double *w, c
                 break;
             }
             if (kstar)
-                kstar[a * N + j] = rt.before ? -1 : (ns - 1) - rt.slot;
+                kstar[a * N + j] = back_offset(ns, rt.before ? -1 : rt.slot);
+            if (kalt)
+                kalt[a * N + j] = back_offset(ns, rt.near_tie ? rt.alt_slot : (rt.before ? -1 : rt.slot));
             for (int c = 0; c < 3; ++c) {
                 neumaier_add(&sE[c], &cE[c], Eij[c]);
                 neumaier_add(&sB[c], &cB[c], Bij[c]);
@@ -575,9 +617,17 @@ int oracle_init_straight(int64_t N, int32_t D, double dt, double t0, const doubl
         T[s] = t0 + kdt;
         for (int64_t i = 0; i < N; ++i) {
             double ui[3] = {u[i], u[N + i], u[2 * N + i]}, vi[3];
+#ifdef MUT_INIT_NO_GAMMA
+            vi[0] = ui[0], vi[1] = ui[1], vi[2] = ui[2];
+#else
             velocity_of(ui, vi);
+#endif
             for (int c = 0; c < 3; ++c) {
+#ifdef MUT_INIT_FORWARD
+                w[((int64_t)s * 3 + c) * N + i] = r[c * N + i] - vi[c] * kdt;
+#else
                 w[((int64_t)s * 3 + c) * N + i] = r[c * N + i] + vi[c] * kdt;
+#endif
                 v[((int64_t)s * 3 + c) * N + i] = vi[c];
             }
         }

@@ -1,4 +1,4 @@
-"""Write c5_subset.json: the oracle's self-fields and bracket checksums at 1024
+"""Write c5_subset.json: the oracle's self-fields and bracket hashes at 1024
 seeded targets of the full-scale workload (N = 262144 electrons, D = 1024
 slots, 5 MeV bunch at 3 R_E in the dipole, straight-line prior history), the
 reference for the GPU's FP64 and mixed-precision passes at that size.
@@ -22,7 +22,7 @@ sys.path.insert(0, os.path.join(ROOT, "tests"))
 
 import oracle  # noqa: E402
 from paper_2605_05543_amd import bunch  # noqa: E402
-from parity import bracket_checksums  # noqa: E402
+from parity import bracket_row_hashes, near_tie_list  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c5_subset.json")
 TARGETS, SEED = 1024, 106
@@ -41,13 +41,14 @@ def main():
     t0 = time.time()
     T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
     E, B, k, SE, SB = orc.fields(T, w, v, -bunch.E_CHARGE, T[-1], r[:, sub], sub, want_kstar=True, want_abs=True)
-    s1, s2 = bracket_checksums(k)
     doc = {
         "what": "oracle self-fields at seeded targets of the N=262144, D=1024 workload; see make_c5_subset.py",
         "oracle_sha256": oracle_source_sha(),
         "targets": sub.tolist(),
         "E": E.tolist(), "B": B.tolist(), "SE": SE.tolist(), "SB": SB.tolist(),
-        "kstar_sum": s1.tolist(), "kstar_weighted_sum": s2.tolist(),
+        # per target: SHA-256 of its k* row (little-endian int32), and the
+        # near ties of the light-cone test as (target, source, k*, other)
+        "kstar_sha256": bracket_row_hashes(k), "near_ties": near_tie_list(k),
         "before_history_fraction": float((k < 0).mean()),
     }
     with open(OUT, "w") as f:

@@ -21,9 +21,23 @@ def assert_fields(tag, got_E, got_B, ref_E, ref_B, SE, SB, tol=FP64_TOL):
 
 
 def assert_kstar(tag, got, ref):
-    bad = np.argwhere(got != ref)
-    print(f"{tag}: k* pairs {got.size}, mismatches {len(bad)}, before-history {np.mean(ref < 0):.3f}", flush=True)
-    assert len(bad) == 0, [(tuple(b), int(got[tuple(b)]), int(ref[tuple(b)])) for b in bad[:5]]
+    """The GPU's bracket of every pair equals the oracle's.  On a near tie of
+    the oracle's light-cone test (``ref.alt`` differs from ``ref`` there) the
+    bracket of the other decision is accepted as well; the number of near
+    ties is printed (none are expected on the workloads: the band is about
+    1e-13 of the light distance)."""
+    got = np.asarray(got)
+    k = np.asarray(ref)
+    alt = getattr(ref, "alt", None)
+    wrong = got != k
+    ties = 0
+    if alt is not None:
+        ties = int(np.count_nonzero(alt != k))
+        wrong &= got != alt
+    bad = np.argwhere(wrong)
+    print(f"{tag}: k* pairs {got.size}, mismatches {len(bad)}, near ties {ties}, "
+          f"before-history {np.mean(k < 0):.3f}", flush=True)
+    assert len(bad) == 0, [(tuple(b), int(got[tuple(b)]), int(k[tuple(b)])) for b in bad[:5]]
 
 
 # Mixed precision: max_i |dE_i| / rms_k |E_k| <= 1e-5 (and the same for B).
@@ -52,13 +66,37 @@ def assert_mixed(tag, got_E, got_B, ref_E, ref_B, SE, SB, tol=MIXED_TOL):
     return out
 
 
-def bracket_checksums(kstar):
-    """Per target of a [m, N] k* array: sum_j (k*_aj + 2) and
-    sum_j (j + 1)(k*_aj + 2), exact in int64 (a wrong bracket on any one
-    pair changes the second sum)."""
-    k = np.asarray(kstar).astype(np.int64) + 2
-    j = np.arange(1, k.shape[1] + 1, dtype=np.int64)
-    return k.sum(axis=1), (k * j).sum(axis=1)
+def bracket_row_hashes(kstar):
+    """Per target of a [m, N] k* array: the SHA-256 of its row as
+    little-endian int32 (a different bracket on any pair changes it)."""
+    import hashlib
+
+    k = np.ascontiguousarray(np.asarray(kstar), dtype="<i4")
+    return [hashlib.sha256(row.tobytes()).hexdigest() for row in k]
+
+
+def near_tie_list(ref):
+    """[(target, source, k*, alt)] of the oracle's near ties."""
+    k = np.asarray(ref)
+    alt = getattr(ref, "alt", None)
+    if alt is None:
+        return []
+    return [(int(a), int(j), int(k[a, j]), int(alt[a, j])) for a, j in np.argwhere(alt != k)]
+
+
+def assert_kstar_hashes(tag, got, hashes, ties):
+    """The GPU's k* rows against stored per-row hashes of the oracle's; on
+    the stored near ties the other decision's bracket is mapped back to the
+    oracle's before hashing."""
+    got = np.array(got, dtype=np.int32, copy=True)
+    for a, j, k, alt in ties:
+        if got[a, j] == alt:
+            got[a, j] = k
+    mine = bracket_row_hashes(got)
+    bad = [a for a, (h1, h2) in enumerate(zip(mine, hashes)) if h1 != h2]
+    print(f"{tag}: k* rows {len(hashes)} x {got.shape[1]} pairs, rows differing {len(bad)}, near ties {len(ties)}",
+          flush=True)
+    assert not bad, bad[:5]
 
 
 def load_c5_subset():
@@ -68,7 +106,9 @@ def load_c5_subset():
     import os
 
     doc = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_subset.json")))
-    out = {k: np.asarray(doc[k]) for k in ("targets", "E", "B", "SE", "SB", "kstar_sum", "kstar_weighted_sum")}
+    out = {k: np.asarray(doc[k]) for k in ("targets", "E", "B", "SE", "SB")}
     out["targets"] = out["targets"].astype(np.int64)
+    out["kstar_sha256"] = list(doc["kstar_sha256"])
+    out["near_ties"] = [tuple(t) for t in doc["near_ties"]]
     out["before_history_fraction"] = doc["before_history_fraction"]
     return out

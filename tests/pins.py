@@ -671,10 +671,270 @@ def pin_adaptive_step(orc):
                 f"next step {dc[0]:.4e} = rule {rule:.4e}")
 
 
+
+# -- Sec. 2.2 sign test against exact rational arithmetic ---------------------------
+
+def _exact_f_sign(r, wk, t, Tk):
+    """Exact sign and relative size of F = (c (t - T_k))^2 - |r - w_k|^2 on
+    the stored doubles, in rational arithmetic (fractions.Fraction holds
+    every double exactly)."""
+    from fractions import Fraction as Fr
+
+    L = Fr(C) * (Fr(float(t)) - Fr(float(Tk)))
+    d = [Fr(float(r[c])) - Fr(float(wk[c])) for c in range(3)]
+    dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
+    F = L * L - dd
+    scale = L * L + dd
+    return (F > 0) - (F < 0), (abs(F) / scale if scale else Fr(0))
+
+
+def _near_cone_targets(T, w, j, rng, count):
+    """Targets placed on (or within a relative 1e-17 .. 1e-9 of) the past
+    light cone of sample s of source j, for random s and directions."""
+    ns = len(T)
+    t = T[-1]
+    xs = []
+    for _ in range(count):
+        s = int(rng.integers(1, ns - 1))
+        L = C * (t - T[s])
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        eps = 0.0 if rng.random() < 0.2 else float(rng.choice([-1, 1]) * 10 ** rng.uniform(-17, -9))
+        xs.append(w[s, :, j] + d * L * (1.0 + eps))
+    return np.array(xs).T
+
+
+def pin_sign_test_exact(orc):
+    """The bracket against exact rational arithmetic on targets placed on or
+    within 1e-17..1e-9 (relative) of a sample's light cone, near the origin
+    and at three Earth radii: wherever the oracle does not flag a near tie
+    its k* is the exact k* = max{k : F_k > 0}; where it flags one, the exact
+    k* is one of the two brackets it names; every pair with a decision
+    closer than 2^-50 (relative) to the cone is flagged, and no pair whose
+    decisions all lie beyond 2^-43 is."""
+    rng = np.random.default_rng(71)
+    bad = []
+    n_flag = n_tight = n_cases = 0
+    for off in (np.zeros(3), np.array([3 * 6.371e6, 0.0, 0.0])):
+        T, w, v = bunch.wiggly_history(3, 16, 1e-13, beta=0.9, accel_rel=0.1, seed=72)
+        w = w + off[None, :, None]
+        for j in range(3):
+            x = _near_cone_targets(T, w, j, rng, 60)
+            out = orc.retarded(T, w[:, :, j:j + 1], v[:, :, j:j + 1], T[-1], x)
+            k, alt = np.asarray(out["kstar"])[:, 0], out["kalt"][:, 0]
+            ns = len(T)
+            for a in range(x.shape[1]):
+                n_cases += 1
+                exact, margins = -1, []
+                for s in range(ns - 2, -1, -1):
+                    sg, rel = _exact_f_sign(x[:, a], w[s, :, j], T[-1], T[s])
+                    margins.append(rel)
+                    if sg > 0:
+                        exact = ns - 1 - s
+                        break
+                flagged = alt[a] != k[a]
+                n_flag += flagged
+                tight = min(margins) < 2.0**-50
+                n_tight += tight
+                if not flagged and k[a] != exact:
+                    bad.append(("wrong", a, int(k[a]), exact))
+                if flagged and exact not in (int(k[a]), int(alt[a])):
+                    bad.append(("neither", a, int(k[a]), int(alt[a]), exact))
+                if tight and not flagged:
+                    bad.append(("unflagged", a, float(min(margins))))
+                if flagged and min(margins) > 2.0**-43:
+                    bad.append(("overflagged", a, float(min(margins))))
+    ok = not bad and n_tight > 20 and n_flag >= n_tight
+    return ok, f"{n_cases} pairs, {n_tight} within 2^-50 of the cone, {n_flag} flagged; problems {bad[:4]}"
+
+
+# -- Sec. 2.1 superposition ------------------------------------------------------------
+
+def _uniform_sources(n, seed, beta_range=(0.2, 0.95), spread=1e-3):
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((3, n))
+    d /= np.linalg.norm(d, axis=0)
+    vel = rng.uniform(*beta_range, n) * C * d
+    w_now = spread * rng.standard_normal((3, n))
+    return w_now, vel
+
+
+def pin_superposition_heaviside_feynman(orc):
+    """Twelve uniformly moving sources (beta 0.2-0.95, pairs in and before
+    the history): each component of the oracle's field at every target
+    equals math.fsum of the per-source Heaviside-Feynman fields within
+    1e-14 of sum_j |E_j|, and S_E, S_B equal the fsum of the closed-form
+    magnitudes to 1e-14.  Then an antipodal set (sources at +-R_k about a
+    target, each pair with one velocity, so the exact fields cancel): the
+    oracle's field there is below 1e-14 of sum_j |E_j|."""
+    w_now, vel = _uniform_sources(12, 81)
+    T, w, v = bunch.uniform_history(64, 1e-13, w_now, vel)
+    rng = np.random.default_rng(82)
+    x = 2e-3 * rng.standard_normal((3, 40))
+    E, B, SE, SB = orc.fields(T, w, v, -QE, T[-1], x, want_abs=True)
+    worst = worst_s = 0.0
+    for a in range(x.shape[1]):
+        Eh, Bh = heaviside_feynman(x[:, a:a + 1] - w_now, vel, -QE)
+        sE, sB = np.linalg.norm(Eh, axis=0), np.linalg.norm(Bh, axis=0)
+        for c in range(3):
+            worst = max(worst, abs(E[c, a] - math.fsum(Eh[c])) / math.fsum(sE),
+                        abs(B[c, a] - math.fsum(Bh[c])) / math.fsum(sB))
+        worst_s = max(worst_s, abs(SE[a] / math.fsum(sE) - 1), abs(SB[a] / math.fsum(sB) - 1))
+    # antipodal set about the target at x0
+    half, hvel = _uniform_sources(4, 83)
+    x0 = np.zeros((3, 1))
+    w2 = np.concatenate([half, -half], axis=1)
+    v2 = np.concatenate([hvel, hvel], axis=1)
+    T2, ww, vv = bunch.uniform_history(64, 1e-13, w2, v2)
+    E2, _, S2, _ = orc.fields(T2, ww, vv, -QE, T2[-1], x0, want_abs=True)
+    Eh2, _ = heaviside_feynman(x0 - w2, v2, -QE)
+    exact_zero = all(math.fsum(Eh2[c]) == 0.0 for c in range(3))
+    cancel = float(np.linalg.norm(E2[:, 0]) / S2[0])
+    ok = worst < 1e-14 and worst_s < 1e-14 and exact_zero and cancel < 1e-14
+    return ok, (f"sum vs fsum of closed forms {worst:.2e} of S; S_E, S_B rel err {worst_s:.2e}; "
+                f"antipodal set |E| / S = {cancel:.2e} (closed forms cancel exactly: {exact_zero})")
+
+
+def pin_superposition_sum(orc):
+    """The compensated sum itself: for 64 accelerating sources, the oracle's
+    field with all sources equals math.fsum (correctly rounded) of its
+    single-source fields to Neumaier's bound, |err| <= 3u |sum| +
+    2 N^2 u^2 sum_j |E_j| per component.  Half of the sources are the other
+    half's trajectories reflected through the origin (w -> -w, v -> -v),
+    so at a target there their fields cancel exactly and the sum is zero,
+    where an uncompensated or wrongly compensated sum misses by ~1e-16 of
+    its terms.  S_E = sum_j |E_j| to N u."""
+    u = 2.0**-53
+    rng = np.random.default_rng(91)
+    T, w, v = bunch.wiggly_history(32, 24, 1e-13, beta=0.9, accel_rel=0.1, seed=92)
+    x0 = np.zeros((3, 1))
+    w_all = np.concatenate([w, -w], axis=2)
+    v_all = np.concatenate([v, -v], axis=2)
+    N = w_all.shape[2]
+    x = np.concatenate([x0, 1e-3 * rng.standard_normal((3, 5))], axis=1)
+    E, B, SE, SB = orc.fields(T, w_all, v_all, -QE, T[-1], x, want_abs=True)
+    singles = [orc.fields(T, w_all[:, :, j:j + 1], v_all[:, :, j:j + 1], -QE, T[-1], x) for j in range(N)]
+    worst = 0.0
+    worst_abs = 0.0
+    for a in range(x.shape[1]):
+        for F, idx in ((E, 0), (B, 1)):
+            terms = np.array([sg[idx][:, a] for sg in singles])  # [N, 3]
+            mag = float(np.sum(np.abs(terms)))
+            for c in range(3):
+                ref = math.fsum(terms[:, c])
+                bound = 3 * u * abs(ref) + 2 * N * N * u * u * mag
+                worst = max(worst, abs(F[c, a] - ref) / bound)
+        sE = math.fsum(float(np.linalg.norm(sg[0][:, a])) for sg in singles)
+        worst_abs = max(worst_abs, abs(SE[a] / sE - 1) / (N * u) if sE > 0 else math.inf)
+    cancel = float(np.linalg.norm(E[:, 0]) / SE[0])
+    ok = worst <= 1.0 and worst_abs <= 1.0 and cancel < 1e-20
+    return ok, (f"error / Neumaier bound max {worst:.2f}; S_E error / (N u) {worst_abs:.2f}; "
+                f"cancellation at the centre |E| / S = {cancel:.1e}")
+
+
+def pin_self_exclusion(orc):
+    """Targets on the sources' present positions with self_index = the
+    source: the excluded source is skipped exactly (the field is bit for
+    bit the field of the history without it), and for uniform motion it is
+    the fsum of the other sources' Heaviside-Feynman fields."""
+    T, w, v = bunch.wiggly_history(10, 20, 1e-13, beta=0.9, accel_rel=0.1, seed=93)
+    x = w[-1].copy()
+    E, B = orc.fields(T, w, v, -QE, T[-1], x, np.arange(10))
+    same = True
+    for i in range(10):
+        keep = [j for j in range(10) if j != i]
+        Ei, Bi = orc.fields(T, w[:, :, keep], v[:, :, keep], -QE, T[-1], x[:, i:i + 1])
+        same &= bool(np.array_equal(Ei[:, 0], E[:, i]) and np.array_equal(Bi[:, 0], B[:, i]))
+    w_now, vel = _uniform_sources(10, 94)
+    Tu, wu, vu = bunch.uniform_history(48, 1e-13, w_now, vel)
+    Eu, _, SEu, _ = orc.fields(Tu, wu, vu, -QE, Tu[-1], w_now, np.arange(10), want_abs=True)
+    worst = 0.0
+    for i in range(10):
+        keep = [j for j in range(10) if j != i]
+        Eh, _ = heaviside_feynman(w_now[:, i:i + 1] - w_now[:, keep], vel[:, keep], -QE)
+        worst = max(worst, max(abs(Eu[c, i] - math.fsum(Eh[c])) for c in range(3)) / SEu[i])
+    ok = same and worst < 1e-14
+    return ok, f"excluded source skipped bit for bit: {same}; vs fsum of the others' closed forms {worst:.2e} of S"
+
+
+# -- straight-line prior history ---------------------------------------------------------
+
+def pin_init_straight(orc):
+    """The prior history built from (r, u): slot times end at t0 one step
+    apart; the newest sample is r exactly; every slot's velocity v satisfies
+    u = v / sqrt(1 - v^2/c^2) (a form of gamma other than the oracle's
+    sqrt(1 + u^2/c^2)); consecutive samples differ by v (T_{k+1} - T_k);
+    and the retarded time the oracle finds on this history is the closed
+    form of uniform motion, in and before the history (near the origin to
+    1e-15 gamma^2, the conditioning of 1 - beta^2; at three Earth radii,
+    where the stored samples are rounded to 3.7 nm, to 1e-5 of millimetre
+    distances)."""
+    rng = np.random.default_rng(95)
+    n, D, dt, t0 = 20, 24, 1e-13, 3.7e-12
+    d = rng.standard_normal((3, n))
+    d /= np.linalg.norm(d, axis=0)
+    beta = np.concatenate([[0.05, 0.5, 0.9, 0.999, 0.9999], rng.uniform(0.1, 0.99, n - 5)])
+    g = 1.0 / np.sqrt(1.0 - beta**2)
+    u = d * (g * beta * C)
+    details, ok = [], True
+    for off, tol in ((np.zeros((3, 1)), 1e-15), (np.array([[3 * 6.371e6], [0.0], [0.0]]), 1e-5)):
+        r = off + 1e-3 * rng.standard_normal((3, n))
+        T, w, v = orc.init_straight(r, u, D, dt, t0)
+        k = np.arange(-(D - 1), 1)
+        tgrid = float(np.max(np.abs(T - (t0 + k * dt)))) / dt
+        newest = bool(np.array_equal(w[-1], r))
+        vv = np.sum(v * v, axis=1)  # [D, n]
+        gv = 1.0 / np.sqrt(1.0 - vv / C**2)
+        urel = float(np.max(np.abs(gv[:, None, :] * v - u[None]) / (np.linalg.norm(u, axis=0) * g * g)))
+        same_v = bool(np.all(v == v[-1:]))
+        ulp = np.spacing(np.max(np.abs(w)))
+        seg = float(np.max(np.abs(w[1:] - w[:-1] - v[:-1] * np.diff(T)[:, None, None]))) / ulp
+        x = r[:, :4].mean(axis=1, keepdims=True) + 2e-3 * rng.standard_normal((3, 12))
+        out = orc.retarded(T, w, v, t0, x)
+        worst = 0.0
+        nb = int(np.sum(np.asarray(out["kstar"]) < 0))
+        for a in range(x.shape[1]):
+            for j in range(n):
+                s_exact = uniform_light_distance(x[:, a] - r[:, j], v[-1, :, j] / C)
+                err = abs(C * (t0 - out["tr"][a, j]) / s_exact - 1)
+                worst = max(worst, err / (g[j] ** 2 if off[0, 0] == 0 else 1.0))
+        good = tgrid < 1e-3 and newest and urel < 1e-15 and same_v and seg <= 4 and worst < tol and nb > 0
+        ok &= good
+        details.append(f"|off| {off[0, 0]:.1e}: T grid {tgrid:.1e} dt, newest exact {newest}, u = gamma v "
+                       f"{urel:.1e} gamma^2, segments {seg:.1f} ulp, uniform retarded distance {worst:.1e} "
+                       f"({nb} before)")
+    return ok, "; ".join(details)
+
+
+# -- surrogate features --------------------------------------------------------------------
+
+def pin_mlp_features(orc):
+    """The network's ten pair features on pairs of chosen geometry: the
+    target offset from the source's newest sample in units of sigma_ref, the
+    source's newest velocity over c, its displacement over the last four
+    slots over c times their time span (not 4 dt: the slots are unevenly
+    spaced here), and log1p of the time since the newest slot over dt, in
+    that order, one row per pair."""
+    from oracle import mlp
+
+    sig, dt = 1.5e-3, 1e-13
+    w_n = np.array([[1.0, -4.0], [-2.0, 0.5], [3.0, 2.0]]) * 1e-3
+    want = np.array([[1.0, -2.0, 0.5, 0.3, 0.0, -0.4, 0.25, 0.5, 0.0, 1.0],
+                     [-3.0, 0.0, 2.0, 0.0, 0.6, 0.1, -0.1, 0.2, 0.3, 1.0]])
+    y_i = w_n + sig * want[:, 0:3].T
+    v_n = C * want[:, 3:6].T
+    T_n, T_n4 = 7.0 * dt, 3.7 * dt
+    w_n4 = w_n - want[:, 6:9].T * C * (T_n - T_n4)
+    t = T_n + (math.e - 1.0) * dt
+    got = mlp.features(y_i, w_n, v_n, w_n4, T_n, T_n4, t, dt, sig)
+    err = float(np.max(np.abs(got - want))) if got.shape == want.shape else float("inf")
+    return err < 1e-12, f"features shape {got.shape}, max abs err {err:.1e}"
+
 ALL_PINS = [
     pin_constants, pin_uniform_retarded_time, pin_heaviside_feynman, pin_heaviside_feynman_far, pin_coulomb, pin_before_history_field,
     pin_bracket_bruteforce, pin_tie_goes_older, pin_circle_reconstruction_order, pin_circle_field_convergence,
     pin_larmor, pin_hc_gyration, pin_hc_exb_drift, pin_dipole, pin_step_history, pin_diag,
     pin_transport_free_and_dt_rule, pin_transport_mirror, pin_adaptive_scan, pin_adaptive_step,
-    pin_midpoint_reconstruction,
+    pin_midpoint_reconstruction, pin_sign_test_exact, pin_superposition_heaviside_feynman, pin_superposition_sum,
+    pin_self_exclusion, pin_init_straight, pin_mlp_features,
 ]

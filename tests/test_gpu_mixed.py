@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_2605_05543_amd import bunch
-from parity import assert_kstar, assert_mixed, bracket_checksums, load_c5_subset
+from parity import assert_kstar, assert_mixed, assert_kstar_hashes, load_c5_subset
 
 pytestmark = pytest.mark.gpu
 
@@ -91,7 +91,7 @@ def test_mixed_c3_full_size_sampled(orc, guess):
 def test_mixed_c5_full_size_subset():
     """C5 size (N=262144, D=1024, 5 MeV: gamma = 10.8, so forward pairs have
     1 - eta_hat.beta down to 0.004): the mixed step's fields at 1024 seeded
-    targets against the stored oracle values, and the bracket checksums."""
+    targets against the stored oracle values, and the per-target hashes of k*."""
     wl = bunch.C5
     print("case mixed C5, 1024 stored targets", flush=True)
     ref = load_c5_subset()
@@ -104,9 +104,7 @@ def test_mixed_c5_full_size_subset():
         _, _, k = ctx.fields_at(0.0, r[:, sub], sub, want_kstar=True)
         ctx.step(1)
         Es, Bs = ctx.fields()
-    s1, s2 = bracket_checksums(k)
-    assert np.array_equal(s1, ref["kstar_sum"]) and np.array_equal(s2, ref["kstar_weighted_sum"]), \
-        np.flatnonzero((s1 != ref["kstar_sum"]) | (s2 != ref["kstar_weighted_sum"]))[:5]
+    assert_kstar_hashes("C5 subset", k, ref["kstar_sha256"], ref["near_ties"])
     assert_mixed("mixed C5 (step launch)", Es[:, sub], Bs[:, sub], ref["E"], ref["B"], ref["SE"], ref["SB"])
 
 

@@ -1,9 +1,10 @@
 """Plant one plausible mistake at a time in the oracle (compile-time
 MUT_* switches in oracle/empp_oracle.c) and check that the pins catch it.
 This shows that the pins constrain every step of the oracle: the
-bracket rule, the root, the reconstruction, the LW formula, B, the pusher,
-the dipole, the history update, the adaptive step and the Stage-II
-transport."""
+bracket rule and its near-tie flags, the root, the reconstruction, the LW
+formula, B, the superposition (its compensated sum and the excluded
+source), the prior history, the pusher, the dipole, the history update,
+the adaptive step and the Stage-II transport."""
 import pytest
 
 import oracle
@@ -26,6 +27,12 @@ MUTANTS = [
     "MUT_TRANSPORT_OLD_V",    # Stage-II drift with the velocity before the kick
     "MUT_ADAPT_NO_ALLOW",     # adaptive step ignores the eta_allow cutoff
     "MUT_ADAPT_ETA_PRESENT",  # adaptive step from the present, not retarded, distance
+    "MUT_NO_NEAR_TIE",        # light-cone decisions next to the cone never flagged
+    "MUT_SUM_SKIP_LAST",      # the superposition stops one source short
+    "MUT_SELF_INDEX_IGNORED",  # the excluded source is summed anyway
+    "MUT_NEUMAIER_SIGN",      # the compensation subtracted instead of added
+    "MUT_INIT_NO_GAMMA",      # prior history moves with u instead of u / gamma
+    "MUT_INIT_FORWARD",       # prior history extrapolated forward in time
 ]
 
 
