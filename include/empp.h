@@ -32,8 +32,12 @@
  * its configuration (NULL: the device's null stream).  empp_step and the
  * *_dev calls only enqueue work; calls that return host data synchronise
  * the stream first.  Errors detected by kernels (coincident particles, a
- * negative discriminant) are latched on the device and reported by the
- * next synchronising call (empp_sync, the getters, empp_fields_at).
+ * negative discriminant: the pair's field is then left out of the sum)
+ * are latched on the device and reported, with the first failing
+ * (target, source), by the next call that synchronises: empp_sync,
+ * empp_get_state, empp_get_history, empp_get_fields, empp_get_diag,
+ * empp_step_until_switch, empp_handoff, empp_transport and empp_fields_at
+ * (which reports an error left by an earlier step before its own launch).
  *
  * Threading: a context is bound to one device and must not be used by two
  * threads at once.  Different contexts are independent.
@@ -65,9 +69,12 @@ typedef enum {
 
 typedef enum {
     EMPP_FP64 = 0,  /* everything in double precision                      */
-    EMPP_MIXED = 1  /* FP64 absolute positions/times, FP32 offsets and LW
-                       terms with two-sum accumulation, FP64 re-test of
-                       light-cone signs inside the FP32 rounding band      */
+    EMPP_MIXED = 1  /* FP64 absolute positions and times and every
+                       light-cone sign test (the bracket is the FP64
+                       path's); FP32 root, reconstruction and LW terms
+                       around FP64 quadratic coefficients, with two-sum
+                       accumulation; an FP32 root that fails its residual
+                       test is recomputed in FP64 (a rescue)             */
 } empp_precision;
 
 typedef enum {
@@ -144,7 +151,7 @@ typedef struct {
     uint64_t pairs;        /* (target, source) pairs evaluated               */
     uint64_t before;       /* pairs whose retarded time precedes the history */
     uint64_t probes;       /* light-cone sign tests performed                */
-    uint64_t rescues;      /* FP64 re-tests of FP32 signs (mixed precision)  */
+    uint64_t rescues;      /* FP32 roots recomputed in FP64 (mixed precision) */
     uint64_t fallbacks;    /* guided searches that fell back to bisection    */
 } empp_counters;
 
@@ -162,27 +169,36 @@ void empp_destroy(empp_ctx *ctx);
 
 const char *empp_last_error(void);
 
-/* Set the bunch: positions r[3][N] and proper velocities u[3][N]
- * (u = gamma v, m/s) at time t0 (host arrays).  The history is built by
- * empp_init_history_straight.  EINVAL on non-finite values.             */
+/* Set the bunch (Sec. 2.5): positions r[3][N] and proper velocities
+ * u[3][N] (u = gamma v, m/s) at time t0 (host arrays).  The history is
+ * built by empp_init_history_straight.  EINVAL on non-finite values.    */
 empp_status empp_init_bunch(empp_ctx *ctx, const double *r, const double *u, double t0);
 
-/* Straight-line prior history: slots k = -(D-1)..0 at T_k = t0 + k dt with
- * w_k = r + v0 (k dt), v_k = v0 = u / gamma (the particle coasted with its
- * initial velocity).  The present time becomes t0, step index 0.        */
+/* Straight-line prior history (the stored past the retarded-time search of
+ * Sec. 2.2 needs before the first step): slots k = -(D-1)..0 at
+ * T_k = t0 + k dt with w_k = r + v0 (k dt), v_k = v0 = u / gamma (the
+ * particle coasted with its initial velocity).  The present time becomes
+ * t0, step index 0.  ESTATE before empp_init_bunch.                     */
 empp_status empp_init_history_straight(empp_ctx *ctx);
 
-/* Install an explicit history (host arrays, nslots == D, oldest first,
- * T strictly increasing) and the present proper velocities u[3][N].  The
- * present time is T[nslots-1]; later steps advance it by dt.  EINVAL when
- * a stored speed is >= c or a value is not finite.                       */
+/* Install an explicit history of Sec. 2.2's stored trajectories (host
+ * arrays, nslots == D, oldest first, T strictly increasing) and the
+ * present proper velocities u[3][N].  The present time is T[nslots-1];
+ * later steps advance it by dt.  EINVAL when a stored speed is >= c or a
+ * value is not finite.                                                    */
 empp_status empp_set_history(empp_ctx *ctx, int32_t nslots, const double *T, const double *w,
                              const double *v, const double *u);
 
-/* Advance nsteps fixed steps (asynchronous).                             */
+/* Advance nsteps steps (asynchronous): each is the pair pass of Secs.
+ * 2.1-2.2 (bracket, Eq. dt root, Eqs. linear/linear2 reconstruction, Eqs.
+ * LW_E/LW_B fields summed over j != i), the Higuera-Cary kick of Sec. 2.3
+ * in the self-field plus the dipole of Sec. 2.6, the drift and the history
+ * update; the step is cfg.dt, or the rule of Sec. 2.4 when cfg.adaptive.
+ * ESTATE before a history exists or after the handoff.                  */
 empp_status empp_step(empp_ctx *ctx, int64_t nsteps);
 
-/* Fields at m external points x[3][m] (host) at the present time t (t must
+/* Lienard-Wiechert self-fields (Secs. 2.1-2.2, the same pass as a step's)
+ * at m external points x[3][m] (host) at the present time t (t must
  * equal it exactly: EINVAL otherwise).  self_index[m] (or NULL) names a
  * source to leave out per target (-1: none).  Outputs E[3][m], B[3][m]
  * (self-fields only, no external field) and, if kstar is not NULL,
@@ -208,6 +224,8 @@ empp_status empp_get_history(empp_ctx *ctx, double *T, double *w, double *v);
 /* Self-fields E[3][N], B[3][N] that the last step's push used (host).    */
 empp_status empp_get_fields(empp_ctx *ctx, double *E, double *B);
 
+/* Diagnostics of the present state (host): RMS sizes (Sec. 2.5), centroid,
+ * mean kinetic energy (Sec. 2.7), time, step and last step size.        */
 empp_status empp_get_diag(empp_ctx *ctx, empp_diag *out);
 
 /* Counters accumulated since the last reset (the counting kernels run

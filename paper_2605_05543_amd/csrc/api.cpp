@@ -886,6 +886,10 @@ empp_status empp_fields_at(empp_ctx *ctx, double t, int64_t m, const double *x, 
         return fail(EMPP_EINVAL, "NULL argument");
     if (!all_finite(x, 3 * (uint64_t)m))
         return fail(EMPP_EINVAL, "non-finite target position");
+    // an error latched by earlier asynchronous work (a step) is reported
+    // here as that work's, before this call's own pairs can latch one
+    if ((st = check_err(ctx)) != EMPP_OK)
+        return fail(st, "an earlier step: %s", std::string(g_last_error).c_str());
     const int64_t N = ctx->cfg.n;
     if (self_index)
         for (int64_t a = 0; a < m; ++a)
@@ -1464,6 +1468,9 @@ empp_status empp_handoff(empp_ctx *ctx)
     empp_status st = set_device(ctx);
     if (st != EMPP_OK)
         return st;
+    // the Stage-I steps before the handoff must have succeeded
+    if ((st = check_err(ctx)) != EMPP_OK)
+        return st;
     const double dip_k = ctx->cfg.dipole_b0 * ctx->cfg.dipole_re * ctx->cfg.dipole_re * ctx->cfg.dipole_re;
     HIP_TRY(launch_handoff(ctx->ring_w(), ctx->cfg.depth, ctx->head, ctx->pos(), ctx->u(), ctx->cfg.n, dip_k,
                            ctx->cfg.ext_field, ctx->skey(), ctx->stime(), ctx->t_now, ctx->stream));
@@ -1504,7 +1511,7 @@ empp_status empp_transport(empp_ctx *ctx, double dt_max, double gyro_fraction, i
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     ctx->t_now = t;
     ctx->step += nsteps;
-    return EMPP_OK;
+    return check_err(ctx);
 }
 
 // ---- checkpoint --------------------------------------------------------------

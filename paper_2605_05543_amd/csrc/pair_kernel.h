@@ -177,10 +177,13 @@ struct MixedPair {
 // cancel in FP32.  Writes E, B into f[0..5]; rescued = the FP32 root failed
 // its residual test and was recomputed in FP64.  Returns false on a
 // numerical failure.
-// BRANCH_RESCUE keeps the rare FP64 re-solve a branch; without it the
-// compiler may evaluate it for every pair and select (measured: a branch
-// pays in the bisection pass, 43.2 -> 36.7 ms at N = 65536, D = 512; the
-// guided passes are 1-2 % faster with the compiler's choice).
+// The FP64 re-solve is the same arithmetic in every search mode (refined
+// hardware square root and reciprocal), so fields do not depend on the
+// search.  BRANCH_RESCUE only decides how it is compiled: a branch around
+// it (an empty volatile asm cannot be speculated), or left to the compiler,
+// which may evaluate it for every pair and select (measured: a branch pays
+// in the bisection pass, 43.2 -> 36.7 ms at N = 65536, D = 512; the guided
+// passes are 1-2 % faster with the compiler's choice).
 template <bool BRANCH_RESCUE>
 __device__ __forceinline__ bool lw_pair_mixed(double L1d, MixedPair q, bool before,
                                               float kq, float f[6], bool &rescued)
@@ -203,18 +206,12 @@ __device__ __forceinline__ bool lw_pair_mixed(double L1d, MixedPair q, bool befo
     float tol = 8.0f * 5.9604645e-8f * (fabsf(C2) * dtr * dtr + 2.0f * fabsf(C1h * dtr) + fabsf(C0));
     rescued = !(fabsf(res) <= tol);
     if (rescued) {
-        if constexpr (BRANCH_RESCUE) {
-            // an empty volatile asm cannot be speculated; refined hardware
-            // estimates, both divisors positive
+        if constexpr (BRANCH_RESCUE)
             asm volatile("");
-            double sqd = sqrt_pos(ok ? discd : 1.0);
-            double rd = C1hd <= 0.0 ? C0d * rcp64(sqd - C1hd) : -(C1hd + sqd) * rcp64(C2d);
-            dtr = (float)rd;
-        } else {
-            double sqd = sqrt(ok ? discd : 0.0);
-            double rd = C1hd <= 0.0 ? C0d / (sqd - C1hd) : -(C1hd + sqd) / C2d;
-            dtr = (float)rd;
-        }
+        // refined hardware estimates; both divisors are positive
+        double sqd = sqrt_pos(ok ? discd : 1.0);
+        double rd = C1hd <= 0.0 ? C0d * rcp64(sqd - C1hd) : -(C1hd + sqd) * rcp64(C2d);
+        dtr = (float)rd;
     }
     // FP64: velocity at the root and u = d - (L1/c) v_r + dt (v_r - v_1)
     double inv_hd = before ? 0.0 : q.v1.w;

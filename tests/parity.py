@@ -112,3 +112,21 @@ def load_c5_subset():
     out["near_ties"] = [tuple(t) for t in doc["near_ties"]]
     out["before_history_fraction"] = doc["before_history_fraction"]
     return out
+
+
+def load_c2_steps():
+    """The oracle's free run of the N=8192, D=512 workload at steps 1 and 10
+    (written by tests/golden/make_c2_steps.py)."""
+    import json
+    import os
+
+    doc = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_steps.json")))
+    out = {"targets": np.asarray(doc["targets"], dtype=np.int64), "steps": {}}
+    for s, d in doc["steps"].items():
+        e = {k: np.asarray(d[k]) for k in ("y", "u", "E", "B", "SE", "SB", "sigma")}
+        e["t"] = float(d["t"])
+        e["kstar_sha256"] = list(d["kstar_sha256"])
+        e["near_ties"] = [tuple(t) for t in d["near_ties"]]
+        e["before_history_fraction"] = d["before_history_fraction"]
+        out["steps"][int(s)] = e
+    return out

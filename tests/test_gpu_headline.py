@@ -1,0 +1,169 @@
+"""The benchmark's configuration against the FP64 oracle: the N = 65536,
+D = 512 bunch (1 MeV, sigma = 1 mm at 3 R_E in the dipole) in the launch
+shape the benchmark times, with the surrogate network trained as the
+benchmark trains it (pairs of C2 and C3 bunches, the C3 pairs four steps
+in) and evaluated once per 2^12 targets (the headline path) or per 2^6;
+mixed precision at 1e-5 of the rms field and FP64 at 1e-12, k* exact.  The
+same on a C3-size accelerating history.  Then 500 steps of the headline
+path against 500 steps of the plain FP64 GPU path (all targets), the
+position and field errors stated.
+
+The oracle's inputs are the seeded bunch (or the seeded history) only: the
+network is trained on GPU states, but it changes cost, never results."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_05543_amd import bunch
+from parity import assert_fields, assert_kstar, assert_mixed, mixed_report
+
+pytestmark = pytest.mark.gpu
+
+Q, ME = -bunch.E_CHARGE, bunch.M_ELECTRON
+
+
+def _ctx(wl, precision=0, guess=0, group_log2=0):
+    from paper_2605_05543_amd._lib import Context
+
+    return Context(n=wl.bunch.n, depth=wl.depth, q=Q, m=ME, dt=wl.dt, ext_field=wl.ext_field,
+                   dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re, precision=precision, guess=guess,
+                   guess_group_log2=group_log2)
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.get()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """Network parameters trained as the benchmark does (fewer pairs):
+    2^21 pairs of a C2 bunch and 2^21 of the C3 bunch after four steps."""
+    from paper_2605_05543_amd import surrogate
+
+    print("case headline: training the surrogate", flush=True)
+    wl = bunch.C3
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    s2 = surrogate.draw_samples(bunch.C2, 1 << 21, seed=21)
+    with _ctx(wl) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        ctx.step(4)
+        ctx.surrogate_set(bunch.surrogate_init(0), bunch.sigma_ref_of(r))
+        s3 = ctx.surrogate_samples_torch(1 << 21, seed=23)
+        rep = surrogate.train(ctx, [s2, s3], batch=8192, steps=1536)
+        params = ctx.surrogate_get()
+    print(f"   loss {rep['loss_first']:.3e} -> {rep['loss_last']:.3e}", flush=True)
+    return params, bunch.sigma_ref_of(r)
+
+
+@pytest.fixture(scope="module")
+def c3_reference(orc):
+    """Oracle fields and k* at 1024 seeded targets of the C3 bunch, initial
+    straight-line history."""
+    wl = bunch.C3
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    sub = bunch.target_subset(wl.bunch.n, 1024, 103)
+    T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], r[:, sub], sub, want_kstar=True, want_abs=True)
+    return r, u, sub, (E0, B0, k0, SE, SB)
+
+
+@pytest.mark.parametrize("precision,group_log2", [(1, 12), (1, 6), (0, 12)])
+def test_headline_step_matches_oracle(trained, c3_reference, precision, group_log2):
+    """The step's fields (the launch the benchmark times) and the k* of the
+    same search mode at 1024 seeded targets against the oracle."""
+    from paper_2605_05543_amd._lib import EMPP_GUESS_MLP
+
+    print(f"case headline C3 precision={precision} targets per evaluation 2^{group_log2}", flush=True)
+    params, sig = trained
+    r, u, sub, (E0, B0, k0, SE, SB) = c3_reference
+    wl = bunch.C3
+    with _ctx(wl, precision, 0, group_log2) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        ctx.surrogate_set(params, sig)
+        ctx.set_mode(precision, EMPP_GUESS_MLP)
+        ctx.set_counting(True)
+        _, _, k = ctx.fields_at(0.0, r[:, sub], sub, want_kstar=True)
+        c1 = ctx.counters()
+        ctx.set_counting(True)
+        ctx.step(1)
+        c2 = ctx.counters()
+        Es, Bs = ctx.fields()
+    print(f"   sign tests per pair: fields_at {c1['probes'] / c1['pairs']:.3f}, step {c2['probes'] / c2['pairs']:.3f}; "
+          f"fallbacks {c2['fallbacks']}; rescues {c2['rescues']}", flush=True)
+    assert_kstar("headline C3", k, k0)
+    if precision == 1:
+        assert_mixed("headline C3 (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
+    else:
+        assert_fields("headline C3 FP64 (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_headline_on_accelerating_history(orc, trained, precision):
+    """C3 size on curving histories (every segment accelerates; the
+    straight-line term misses there and the network's correction acts):
+    the headline search mode's step fields and k* at 256 seeded targets."""
+    from paper_2605_05543_amd._lib import EMPP_GUESS_MLP, Context
+
+    print(f"case headline on a C3-size accelerating history, precision={precision}", flush=True)
+    params, sig = trained
+    n, depth, dt = 65536, 512, 1e-13
+    T, w, v = bunch.wiggly_history(n, depth, dt, beta=0.9, sigma=1e-3, accel_rel=0.05, seed=35)
+    g = 1 / np.sqrt(1 - (v[-1] ** 2).sum(0) / bunch.C_LIGHT**2)
+    sub = bunch.target_subset(n, 256, 105)
+    E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], w[-1][:, sub], sub, want_kstar=True, want_abs=True)
+    with Context(n=n, depth=depth, q=Q, m=ME, dt=dt, precision=precision, guess_group_log2=12) as ctx:
+        ctx.set_history(T, w, v, v[-1] * g)
+        ctx.surrogate_set(params, sig)
+        ctx.set_mode(precision, EMPP_GUESS_MLP)
+        ctx.set_counting(True)
+        _, _, k = ctx.fields_at(T[-1], w[-1][:, sub], sub, want_kstar=True)
+        ctx.set_counting(True)
+        ctx.step(1)
+        c = ctx.counters()
+        Es, Bs = ctx.fields()
+    print(f"   sign tests per pair {c['probes'] / c['pairs']:.3f}, fallbacks {c['fallbacks']}", flush=True)
+    assert_kstar("headline accelerating", k, k0)
+    if precision == 1:
+        assert_mixed("headline accelerating (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
+    else:
+        assert_fields("headline accelerating FP64 (step launch)", Es[:, sub], Bs[:, sub], E0, B0, SE, SB)
+
+
+def test_headline_500_steps_against_fp64(trained):
+    """500 steps of the headline path (mixed precision, network per 2^12
+    targets) and of the plain FP64 path from the same bunch, all 65536
+    particles: max |dy| / sigma and the last step's field error over the
+    rms field, stated and bounded (1e-6 of sigma, 1e-5 of the field)."""
+    from paper_2605_05543_amd._lib import EMPP_GUESS_MLP
+
+    print("case headline 500 steps vs FP64", flush=True)
+    params, sig = trained
+    wl = bunch.C3
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    out = {}
+    for name, precision, guess in (("fp64", 0, 0), ("headline", 1, EMPP_GUESS_MLP)):
+        with _ctx(wl, precision, 0, 12) as ctx:
+            ctx.init_bunch(r, u, 0.0)
+            ctx.init_history_straight()
+            if guess:
+                ctx.surrogate_set(params, sig)
+                ctx.set_mode(precision, guess)
+            for k in range(5):
+                ctx.step(wl.steps // 5)
+                print(f"   {name}: {(k + 1) * wl.steps // 5} steps", flush=True)
+            out[name] = (ctx.state(), ctx.fields(), ctx.diag())
+    (ra, ua, ta, sa), (Ea, Ba), da = out["fp64"]
+    (rb, ub, tb, sb), (Eb, Bb), db = out["headline"]
+    assert sa == sb == wl.steps and ta == tb
+    sigma = float(np.mean(da["sigma"]))
+    dy = float(np.max(np.abs(rb - ra))) / sigma
+    du = float(np.max(np.linalg.norm(ub - ua, axis=0) / np.linalg.norm(ua, axis=0)))
+    rep = mixed_report("headline vs FP64 after 500 steps", Eb, Bb, Ea, Ba, np.ones(Ea.shape[1]),
+                       np.ones(Ea.shape[1]))
+    dsig = max(abs(db["sigma"][k] / da["sigma"][k] - 1) for k in range(3))
+    print(f"   500 steps: max|dy|/sigma {dy:.2e}, max|du|/|u| {du:.2e}, sigma rel diff {dsig:.1e}", flush=True)
+    assert dy < 1e-6 and du < 1e-6
+    assert rep["E"]["max_over_rms"] < 1e-5 and rep["B"]["max_over_rms"] < 1e-5

@@ -1,9 +1,12 @@
-"""Mixed-precision path (FP32 offsets, sign tests and LW terms; FP64
-positions, residual at the root and rescues) against the FP64 oracle.
+"""Mixed-precision path against the FP64 oracle.  Every light-cone sign
+test stays FP64 (the bracket search is the FP64 path's); the root, the
+reconstruction and the LW terms run in FP32 around FP64 quadratic
+coefficients, with two-sum accumulation, and an FP32 root that fails its
+residual test is recomputed in FP64 (a rescue).
 
-k* must be bit-identical to the oracle's (an FP32 sign test is only
-trusted outside its rounding band).  Fields: max_i |dE_i| / rms_k |E_k| <=
-1e-5 (same for B); the spread of per-target relative errors is printed."""
+k* must equal the oracle's (either bracket only on a flagged near tie).
+Fields: max_i |dE_i| / rms_k |E_k| <= 1e-5 (same for B); the spread of
+per-target relative errors is printed."""
 import numpy as np
 import pytest
 

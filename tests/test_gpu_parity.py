@@ -8,8 +8,8 @@ import pytest
 
 import oracle
 from paper_2605_05543_amd import bunch
-from parity import (FP64_TOL, MIXED_TOL, assert_fields, assert_kstar, assert_mixed, assert_kstar_hashes,
-                    field_errors, load_c5_subset)
+from parity import (FP64_TOL, MIXED_TOL, assert_fields, assert_kstar, assert_kstar_hashes, assert_mixed,
+                    field_errors, load_c2_steps, load_c5_subset)
 
 pytestmark = pytest.mark.gpu
 
@@ -164,6 +164,45 @@ def test_c2_subset_and_invariants(orc):
     assert np.all(np.isfinite(wg))
 
 
+def test_c2_free_run_against_the_oracles():
+    """C2 (N=8192, D=512, 2 MeV): the GPU's free run from the seeded bunch
+    against the oracle's own free run, stored at steps 1 and 10 for the 64
+    seeded targets (tests/golden/c2_steps.json, written by an oracle-only
+    script).  Step 1: positions to rounding, k* of the 64 targets exact
+    (one hash per target row), fields within 1e-12.  Step 10: the
+    divergence of positions and fields is stated, and bounded by 1e-12 of
+    sigma and 1e-10 of the rms field."""
+    wl = bunch.C2
+    ref = load_c2_steps()
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    n = wl.bunch.n
+    sub = ref["targets"]
+    done = 0
+    with _ctx(n, wl.depth, wl.dt) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        for s in sorted(ref["steps"]):
+            print(f"case C2 free run, step {s}", flush=True)
+            ctx.step(s - done)
+            done = s
+            rg, ug, t, _ = ctx.state()
+            e = ref["steps"][s]
+            assert t == e["t"]
+            E, B, k = ctx.fields_at(t, rg[:, sub], sub, want_kstar=True)
+            sig = float(np.mean(e["sigma"]))
+            dy = float(np.max(np.abs(rg[:, sub] - e["y"]))) / sig
+            du = float(np.max(np.abs(ug[:, sub] - e["u"]) / np.max(np.abs(e["u"]))))
+            e1, e2 = field_errors(E, e["E"], e["SE"])
+            print(f"   step {s}: max|dy|/sigma {dy:.2e}, max|du|/|u| {du:.2e}, fields err/S {e1:.2e}, "
+                  f"err/rms {e2:.2e}", flush=True)
+            if s == 1:
+                assert dy < 1e-15 and du < 1e-15
+                assert_kstar_hashes(f"C2 step {s}", k, e["kstar_sha256"], e["near_ties"])
+                assert_fields(f"C2 step {s}", E, B, e["E"], e["B"], e["SE"], e["SB"])
+            else:
+                assert dy < 1e-12 and du < 1e-12 and e2 < 1e-10
+
+
 def test_c3_full_size_sampled(orc):
     """C3 size (N=65536, D=512, dipole at 3 R_E): the step's fields at 1024
     seeded targets against the oracle, and k* of those targets (6.7e7
@@ -213,6 +252,34 @@ def test_errors_are_reported(orc):
         # the same target with source 4 excluded is fine
         E, B = ctx.fields_at(T[-1], x, np.array([4]))
         assert np.all(np.isfinite(E))
+
+
+def test_step_error_reaches_every_getter():
+    """Two particles on one position: the step's pair kernels latch the
+    coincident pair; the next synchronising call reports ENUMERIC naming
+    both particles, whichever it is (state, diag, fields, history, fields_at
+    after a step, handoff), and the error is cleared once reported."""
+    from paper_2605_05543_amd._lib import EMPP_ENUMERIC, EmppError
+
+    print("case step error reaches the getters", flush=True)
+    n, depth, dt = 16, 8, 1e-13
+    r, u = bunch.gaussian_bunch(bunch.BunchSpec(n, (1e-3, 1e-3, 1e-3), 1.0, seed=21))
+    r[:, 7] = r[:, 3]
+    getters = {"state": lambda c: c.state(), "diag": lambda c: c.diag(), "fields": lambda c: c.fields(),
+               "history": lambda c: c.history(), "fields_at": lambda c: c.fields_at(c.state_t, r[:, :1] + 1e-3),
+               "handoff": lambda c: c.handoff()}
+    for name, call in getters.items():
+        with _ctx(n, depth, dt) as ctx:
+            ctx.init_bunch(r, u, 0.0)
+            ctx.init_history_straight()
+            ctx.step(1)
+            ctx.state_t = dt
+            with pytest.raises(EmppError) as ei:
+                call(ctx)
+            print(f"   {name}: {ei.value}", flush=True)
+            assert ei.value.status == EMPP_ENUMERIC
+            assert "source 3" in str(ei.value) or "source 7" in str(ei.value)
+            ctx.sync()  # reported once, then cleared
 
 
 @pytest.mark.parametrize("n,depth,m", [(48, 64, 300), (300, 128, 257)])
