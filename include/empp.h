@@ -214,6 +214,24 @@ empp_status empp_fields_at_dev(empp_ctx *ctx, double t, int64_t m, const double 
                                const int64_t *self_index_dev, double *E_dev, double *B_dev,
                                int32_t *kstar_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * fields as empp_fields_at_dev, with the same arguments and layouts,
+ * asynchronous on the context's stream, but the call allocates nothing.
+ * The per-chunk field partials of its pass go to a fixed 128 MiB device
+ * array the library holds on every GPU it runs on until the process ends
+ * (its address is looked up once per device by empp_create), so at most
+ * floor(128 MiB / (96 B x source chunks)) targets fit one call (10922 with
+ * the 128 chunks of N = 65536): EINVAL beyond that.  Guess modes
+ * EMPP_GUESS_MLP and EMPP_GUESS_MLP_PAIR are EUNSUPPORTED here.  Results
+ * are bit-identical to empp_fields_at_dev's (same chunks, same merge
+ * order).  All calls on one GPU share the array, which keeps the last
+ * call's partials: calls that overlap on one GPU (two streams, two
+ * threads) race and must be serialised by the caller.                    */
+empp_status empp_fields_at_dev_noalloc(empp_ctx *ctx, double t, int64_t m, const double *x_dev,
+                                       const int64_t *self_index_dev, double *E_dev, double *B_dev,
+                                       int32_t *kstar_dev);
+
 /* Present positions r[3][N], proper velocities u[3][N], time and step
  * index (host; any output may be NULL).                                  */
 empp_status empp_get_state(empp_ctx *ctx, double *r, double *u, double *t, int64_t *step);

@@ -24,6 +24,7 @@ EMPP_GUESS_BISECT, EMPP_GUESS_MLP, EMPP_GUESS_BALLISTIC, EMPP_GUESS_MLP_PAIR, EM
 EXPORTS = [
     "empp_workspace_size", "empp_create", "empp_destroy", "empp_last_error", "empp_init_bunch",
     "empp_init_history_straight", "empp_set_history", "empp_step", "empp_fields_at", "empp_fields_at_dev",
+    "empp_fields_at_dev_noalloc",
     "empp_get_state", "empp_get_history", "empp_get_fields", "empp_get_diag", "empp_set_counting",
     "empp_get_counters", "empp_sync", "empp_set_mode", "empp_set_timing", "empp_get_timing",
     "empp_surrogate_set", "empp_surrogate_get", "empp_surrogate_samples", "empp_surrogate_samples_dev",
@@ -106,6 +107,7 @@ def _load():
         "empp_step": [_P, _I64],
         "empp_fields_at": [_P, _D, _I64, _P, _P, _P, _P, _P],
         "empp_fields_at_dev": [_P, _D, _I64, _P, _P, _P, _P, _P],
+        "empp_fields_at_dev_noalloc": [_P, _D, _I64, _P, _P, _P, _P, _P],
         "empp_get_state": [_P, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_I64)],
         "empp_get_history": [_P, _P, _P, _P],
         "empp_get_fields": [_P, _P, _P],
@@ -205,6 +207,10 @@ def empp_fields_at(h, t, x, n_src, self_index=None, want_kstar=False):
 
 def empp_fields_at_dev(h, t, m, x_ptr, self_ptr, E_ptr, B_ptr, kstar_ptr=None):
     _check(lib.empp_fields_at_dev(h, float(t), int(m), x_ptr, self_ptr, E_ptr, B_ptr, kstar_ptr))
+
+
+def empp_fields_at_dev_noalloc(h, t, m, x_ptr, self_ptr, E_ptr, B_ptr, kstar_ptr=None):
+    _check(lib.empp_fields_at_dev_noalloc(h, float(t), int(m), x_ptr, self_ptr, E_ptr, B_ptr, kstar_ptr))
 
 
 def empp_get_state(h, n):

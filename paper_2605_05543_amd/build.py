@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libempp.so")
 
-SOURCES = ["api.cpp", "pair_fp64.hip", "pair_mixed.hip", "push.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "pair_fp64.hip", "pair_mixed.hip", "push.hip", "mlp.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

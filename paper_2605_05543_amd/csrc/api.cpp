@@ -50,6 +50,8 @@ hipError_t launch_group_centroid(const double4 *ring_w, const int32_t *order, in
                                  double3 *centroid, hipStream_t s);
 hipError_t launch_group_centroid_x(const double *x, int64_t m, int group, double3 *centroid, hipStream_t s);
 hipError_t launch_merge_centroids(const double3 *cent64, int64_t m, int ratio, double3 *out, hipStream_t s);
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch(int device, void **out);
 }  // namespace empp
 
 using namespace empp;
@@ -252,6 +254,7 @@ struct empp_ctx {
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     bool owns_ws = false;
+    void *scratch = nullptr;  // this device's copy of the allocation-free entry point's scratch
     int nsplit = 1;
     int tile = 1;
     // state
@@ -533,6 +536,15 @@ empp_status empp_create(const empp_config *cfg, empp_ctx **out)
     if ((st = set_device(ctx)) != EMPP_OK) {
         delete ctx;
         return st;
+    }
+    // set-up of the allocation-free entry point: the address of this
+    // device's scratch array (looked up once per device)
+    {
+        hipError_t e = noalloc_scratch(cfg->device, &ctx->scratch);
+        if (e != hipSuccess) {
+            delete ctx;
+            return fail(EMPP_EDEVICE, "scratch address on device %d: %s", cfg->device, hipGetErrorString(e));
+        }
     }
     if (cfg->workspace) {
         if (cfg->workspace_bytes < ctx->L.total || ((uintptr_t)cfg->workspace % kAlign) != 0) {
@@ -872,6 +884,42 @@ empp_status empp_fields_at_dev(empp_ctx *ctx, double t, int64_t m, const double 
     if (!x_dev || !E_dev || !B_dev)
         return fail(EMPP_EINVAL, "NULL argument");
     return fields_dev_impl(ctx, m, x_dev, self_dev, E_dev, B_dev, kstar_dev);
+}
+
+empp_status empp_fields_at_dev_noalloc(empp_ctx *ctx, double t, int64_t m, const double *x_dev,
+                                       const int64_t *self_dev, double *E_dev, double *B_dev, int32_t *kstar_dev)
+{
+    empp_status st = fields_precheck(ctx, t, m);
+    if (st != EMPP_OK)
+        return st;
+    if (m == 0)
+        return EMPP_OK;
+    if (!x_dev || !E_dev || !B_dev)
+        return fail(EMPP_EINVAL, "NULL argument");
+    if (ctx->cfg.guess == EMPP_GUESS_MLP || ctx->cfg.guess == EMPP_GUESS_MLP_PAIR)
+        return fail(EMPP_EUNSUPPORTED, "the allocation-free fields call runs the bisection or the straight-line guess");
+    // the chunk partials, nsplit x 12 doubles per target, live in the scratch array
+    const uint64_t per_target = (uint64_t)ctx->nsplit * 12 * sizeof(double);
+    const int64_t m_max = (int64_t)(noalloc_scratch_bytes() / per_target);
+    if (m > m_max)
+        return fail(EMPP_EINVAL, "m = %lld targets exceed the allocation-free call's maximum of %lld (%llu-byte scratch, "
+                    "%d source chunks)", (long long)m, (long long)m_max, (unsigned long long)noalloc_scratch_bytes(),
+                    ctx->nsplit);
+    if (!ctx->scratch)
+        return fail(EMPP_ESTATE, "no scratch address for device %d", ctx->cfg.device);
+    PairParams p = pair_params(ctx);
+    p.x = x_dev;
+    p.self_index = self_dev;
+    p.m = m;
+    p.kstar = kstar_dev;
+    p.part = reinterpret_cast<double *>(ctx->scratch);
+    // launched directly: no timing events, no guess buffers
+    hipError_t e = ctx->cfg.precision == EMPP_MIXED ? launch_pair_mixed(p, ctx->stream, kstar_dev != nullptr, ctx->counting)
+                                                    : launch_pair_fp64(p, ctx->stream, kstar_dev != nullptr, ctx->counting);
+    if (e != hipSuccess)
+        return fail(EMPP_EDEVICE, "pair pass: %s", hipGetErrorString(e));
+    HIP_TRY(launch_merge_fields(p.part, ctx->nsplit, m, E_dev, B_dev, ctx->stream));
+    return EMPP_OK;
 }
 
 empp_status empp_fields_at(empp_ctx *ctx, double t, int64_t m, const double *x, const int64_t *self_index,
