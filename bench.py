@@ -38,31 +38,36 @@ MLP_FLOP_EVAL = 2 * (10 * 128 + 128 * 128 + 128)
 #   accumulation of E and B:                        6
 FLOP_PROBE = 9
 GUESS_NAMES = ["bisect", "mlp", "ballistic", None, "previous"]
+# The roofline's algorithmic work per pair: the plain path's estimate of the
+# measurement plan (about 10 sign tests of 11 flops, 33 for the quadratic,
+# 22 for the reconstruction, 80 for the LW terms, 6 for the sum, in history;
+# 2 sign tests and no acceleration terms before it; the workload's mix).
+ROOFLINE_FLOP_PER_PAIR = 220.0
 FLOP_INRING = 32 + 20 + 69 + 6
 FLOP_BEFORE = 32 + 6 + 48 + 6
 
 
 def measured_traffic():
-    """HBM bytes per launch of the FP64 pair kernel from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
-    has changed since those counters were taken."""
+    """HBM bytes per launch of the pair kernels from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, {path: bytes}, or {} when the kernel
+    sources have changed since those counters were taken."""
     import re
 
-    prof = os.path.join(ROOT, "profiles", "pair_fp64_c3_traffic.md")
+    prof = os.path.join(ROOT, "profiles", "pair_kernels_c3_traffic.md")
     try:
         text = open(prof).read()
     except OSError:
-        return None
-    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+        return {}
     m_h = re.search(r"sources: " + " ".join(KERNEL_SOURCES) + r" sha256 ([0-9a-f]+)", text)
-    if not (m_b and m_h):
-        return None
-    return float(m_b.group(1)) if kernel_sources_sha().startswith(m_h.group(1)) else None
+    if not m_h or not kernel_sources_sha().startswith(m_h.group(1)):
+        return {}
+    return {m.group(1): float(m.group(2)) for m in re.finditer(r"traffic_bytes_per_launch\[([a-z0-9:/]+)\]:\s*([0-9.eE+]+)",
+                                                              text)}
 
 
-# the sources the FP64 pair kernel is compiled from (traffic counters are
+# the sources the pair kernels are compiled from (traffic counters are
 # valid while they are unchanged)
-KERNEL_SOURCES = ("pair_fp64.hip", "pair_kernel.h", "pair_common.h", "empp_dev.h")
+KERNEL_SOURCES = ("pair_fp64.hip", "pair_mixed.hip", "pair_kernel.h", "pair_common.h", "empp_dev.h")
 
 
 def kernel_sources_sha():
@@ -105,12 +110,19 @@ def train_surrogate(ctx, wl, r, epochs=2):
     return rep
 
 
-def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_log2=0):
+def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_log2=0, keep_fields=False,
+             stage2=None):
+    """Time one search mode on the workload: ``steps`` steps after
+    ``warmup``, kernel times from HIP events.  With ``keep_fields`` the
+    path's step fields at the initial state (all particles) are returned
+    too, for the error check against the oracle; with ``stage2`` (c5) the
+    run continues with the handoff and Stage-II transport."""
     import torch
 
     from paper_2605_05543_amd._lib import Context
 
     n = wl.bunch.n
+    spec = f"{['fp64', 'mixed'][precision]}:{GUESS_NAMES[guess]}" + (f"/{group_log2}" if group_log2 else "")
     ctx = Context(n=n, depth=wl.depth, q=-bunch.E_CHARGE, m=bunch.M_ELECTRON, dt=wl.dt, ext_field=wl.ext_field,
                   dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re, precision=precision,
                   guess=4 if guess == 4 else 0, guess_group_log2=group_log2)
@@ -128,22 +140,29 @@ def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_lo
     if warmup:
         ctx.step(warmup)
     ctx.sync()
+    d0 = ctx.diag()
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.step(steps)
+    done = 0
+    while done < steps:  # progress every 100 steps on long runs
+        k = min(100, steps - done)
+        ctx.step(k)
+        done += k
+        if steps > 100:
+            ctx.sync()
+            log(f"    {spec}: {done} steps")
     ctx.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tim = ctx.timing()
     ctx.set_timing(False)
     d = ctx.diag()
-    ctx.close()
     pairs = n * (n - 1)
     pair_ms = tim["pair_ms"] / max(1, tim["pair_launches"])
     flops = algorithmic_flops(cnt)
     out = {
-        "precision": ["fp64", "mixed"][precision], "guess": GUESS_NAMES[guess],
+        "precision": ["fp64", "mixed"][precision], "guess": GUESS_NAMES[guess], "spec": spec,
         "pair_evals_per_s": pairs * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
         "pair_kernel_ms": pair_ms, "push_kernel_ms": tim["push_ms"] / max(1, tim["push_launches"]),
         "probes_per_pair": cnt["probes"] / cnt["pairs"], "before_history_fraction": cnt["before"] / cnt["pairs"],
@@ -167,13 +186,44 @@ def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_lo
         train_rep["bf16_tflops"] = (train_rep["steps"] * train_rep["batch"] * 3 * MLP_FLOP_EVAL
                                     / train_rep["seconds"] / 1e12)
         out["surrogate_training"] = train_rep
-    log(f"  {out['precision']}/{out['guess']}: {out['pair_evals_per_s']:.3e} pair-evals/s, "
-        f"{out['ms_per_step']:.2f} ms/step, pair kernel {pair_ms:.2f} ms, {out['probes_per_pair']:.2f} probes/pair, "
-        f"{out['achieved_tflops']:.1f} TFLOP/s algorithmic")
+    if stage2:
+        # Stage I -> II (Sec. 2.7): handoff, then transport in the dipole
+        sig1 = d["sigma"]
+        ctx.handoff()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        left = stage2["steps"]
+        while left > 0:
+            k = min(20000, left)
+            ctx.transport(stage2["dt_max"], stage2["gyro_fraction"], k)
+            left -= k
+            log(f"    transport: {stage2['steps'] - left} steps, t = {ctx.state()[2]:.4e} s")
+        el2 = time.perf_counter() - t1
+        d2 = ctx.diag()
+        out["stage2"] = {"steps": stage2["steps"], "dt_max": stage2["dt_max"], "gyro_fraction": stage2["gyro_fraction"],
+                         "seconds": el2, "steps_per_s": stage2["steps"] / el2, "t_end": d2["t"],
+                         "sigma_stage1_start": d0["sigma"], "sigma_handoff": sig1, "sigma_end": d2["sigma"],
+                         "sigma_growth_stage1": [b / a for a, b in zip(d0["sigma"], sig1)],
+                         "sigma_growth_stage2": [b / a for a, b in zip(sig1, d2["sigma"])]}
+        ctx.close()
+        ctx = None
+    if keep_fields and ctx is not None:
+        # the path's step fields at the initial state, in the timed launch shape
+        ctx.init_history_straight()
+        ctx.step(1)
+        out["_fields"] = ctx.fields()
+    if ctx is not None:
+        ctx.close()
+    log(f"  {spec}: {out['pair_evals_per_s']:.3e} pair-evals/s, {out['ms_per_step']:.2f} ms/step, pair kernel "
+        f"{pair_ms:.2f} ms, {out['probes_per_pair']:.2f} probes/pair")
     return out
 
 
 def cpu_baseline(wl, r, u, target_seconds=15.0):
+    """The oracle's rate on a bounded sample of the workload (fields at
+    seeded targets x all sources at the initial state), on all host threads
+    and on one.  Returns the record and the oracle's fields at the sample's
+    targets (for the GPU paths' error)."""
     import oracle
 
     orc = oracle.get()
@@ -187,7 +237,7 @@ def cpu_baseline(wl, r, u, target_seconds=15.0):
     m = int(max(8, min(n, rate * target_seconds)))
     sub = bunch.target_subset(n, m, 1002)
     t0 = time.perf_counter()
-    orc.fields(T, w, v, -bunch.E_CHARGE, T[-1], r[:, sub], sub)
+    E, B, SE, SB = orc.fields(T, w, v, -bunch.E_CHARGE, T[-1], r[:, sub], sub, want_abs=True)
     el = time.perf_counter() - t0
     value = m * (n - 1) / el
     log(f"  cpu oracle: {m} targets x {n - 1} sources in {el:.1f} s on {threads} threads: {value:.3e} pair-evals/s")
@@ -199,11 +249,39 @@ def cpu_baseline(wl, r, u, target_seconds=15.0):
     el1 = time.perf_counter() - t0
     value1 = m1 * (n - 1) / el1
     log(f"  cpu oracle, one thread: {m1} targets in {el1:.1f} s: {value1:.3e} pair-evals/s")
-    return {"value": value, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"fields at {m} seeded targets x {n - 1} sources, one step of {wl.name} "
-                      f"(FP64 C oracle, linear history scan), {el:.1f} s",
-            "single_core_value": value1,
-            "single_core_sample": f"{m1} seeded targets x {n - 1} sources on one thread, {el1:.1f} s"}
+    rec = {"value": value, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"fields at {m} seeded targets x {n - 1} sources, one step of {wl.name} "
+                     f"(FP64 C oracle, linear history scan), {el:.1f} s",
+           "single_core_value": value1,
+           "single_core_sample": f"{m1} seeded targets x {n - 1} sources on one thread, {el1:.1f} s"}
+    return rec, (sub, E, B, SE, SB)
+
+
+def field_error(got, ref, S):
+    """max_i |d_i| / rms_k |ref_k| and max_i |d_i| / S_i for [3, m] arrays."""
+    d = np.linalg.norm(got - ref, axis=0)
+    rms = np.sqrt(np.mean(np.sum(ref * ref, axis=0)))
+    return float(d.max() / rms), float(np.max(d / S))
+
+
+def error_vs_oracle(fields, ref):
+    sub, E0, B0, SE, SB = ref
+    E, B = fields
+    e_rms, e_s = field_error(E[:, sub], E0, SE)
+    b_rms, b_s = field_error(B[:, sub], B0, SB)
+    return {"targets": int(len(sub)), "E_max_over_rms": e_rms, "B_max_over_rms": b_rms, "E_max_over_S": e_s,
+            "B_max_over_S": b_s}
+
+
+def c5_error(fields):
+    """Error of step fields against the stored oracle values at 1024 seeded
+    targets of the N = 262144 workload (tests/golden/c5_subset.json)."""
+    import json
+
+    doc = json.load(open(os.path.join(ROOT, "tests", "golden", "c5_subset.json")))
+    sub = np.asarray(doc["targets"], dtype=np.int64)
+    ref = (sub, np.asarray(doc["E"]), np.asarray(doc["B"]), np.asarray(doc["SE"]), np.asarray(doc["SB"]))
+    return error_vs_oracle(fields, ref)
 
 
 def main():
@@ -211,12 +289,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-epochs", type=int, default=2, help="passes over the surrogate's training pairs")
-    ap.add_argument("--paths", default="fp64:bisect,mixed:mlp/12,mixed:mlp,mixed:bisect,mixed:ballistic,"
-                                        "fp64:ballistic,fp64:previous",
-                    help="precision:search[/k], k = log2 of the targets per surrogate evaluation")
+    ap.add_argument("--paths", default=None,
+                    help="precision:search[/k], k = log2 of the targets per surrogate evaluation (c3 default: "
+                         "fp64:bisect,mixed:mlp/12,mixed:mlp,mixed:bisect,mixed:ballistic,fp64:ballistic,"
+                         "fp64:previous; c5: fp64:bisect,mixed:mlp/12)")
+    ap.add_argument("--transport-steps", type=int, default=100000, help="c5: Stage-II steps after the handoff")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -235,6 +315,10 @@ def main():
               "targets, each GPU holding a replica of the history ring). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     wl = {"c1": bunch.C1, "c2": bunch.C2, "c3": bunch.C3, "c5": bunch.C5}[args.workload]
+    c5 = wl is bunch.C5
+    paths = args.paths or ("fp64:bisect,mixed:mlp/12" if c5 else
+                           "fp64:bisect,mixed:mlp/12,mixed:mlp,mixed:bisect,mixed:ballistic,fp64:ballistic,"
+                           "fp64:previous")
     import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -243,20 +327,29 @@ def main():
     pmap = {"fp64": 0, "mixed": 1}
     gmap = {name: k for k, name in enumerate(GUESS_NAMES) if name}
     results = []
-    for spec in args.paths.split(","):
+    for k, spec in enumerate(paths.split(",")):
         p, g = spec.split(":")
-        g, _, k = g.partition("/")
-        results.append(run_path(wl, r, u, pmap[p], gmap[g], args.steps, args.warmup, args.train_epochs,
-                                int(k or 0)))
+        g, _, lg = g.partition("/")
+        head_candidate = p == "mixed" and g == "mlp"
+        st2 = ({"steps": args.transport_steps, "dt_max": 1e-7, "gyro_fraction": 1 / 32}
+               if c5 and head_candidate else None)
+        results.append(run_path(wl, r, u, pmap[p], gmap[g], args.steps, args.warmup, args.train_epochs, int(lg or 0),
+                                keep_fields=(k == 0 or head_candidate) and not st2, stage2=st2))
     plain = results[0]
     # headline: the mixed-precision surrogate-guided path when it was run,
     # else the first mixed path, else the plain FP64 path
     mixed = [x for x in results if x["precision"] == "mixed"]
     head = next((x for x in mixed if x["guess"] == "mlp"), mixed[0] if mixed else plain)
+    ball = next((x for x in results if x["spec"] == "fp64:ballistic"), None)
     n = wl.bunch.n
-    launch_flops = plain["flops_per_pair"] * n * (n - 1)
-    achieved = launch_flops / (plain["pair_kernel_ms"] * 1e-3) / 1e12
-    traffic = measured_traffic() if wl is bunch.C3 else None
+    pairs = n * (n - 1)
+    achieved = ROOFLINE_FLOP_PER_PAIR * pairs / (plain["pair_kernel_ms"] * 1e-3) / 1e12
+    traffic = measured_traffic() if wl is bunch.C3 else {}
+    for x in results:
+        tb = traffic.get(x["spec"])
+        x["hbm_bytes_per_launch"] = tb
+        x["hbm_bytes_per_pair"] = tb / pairs if tb else None
+    tplain = traffic.get(plain["spec"])
     line = {
         "metric": "LW pair-evals/s at N=65536 (FP32+surrogate vs FP64 plain, <=1e-5 rel err)",
         "value": head["pair_evals_per_s"],
@@ -271,21 +364,33 @@ def main():
         "dtype": "f64" if head["precision"] == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "n": n, "depth": wl.depth, "dt": wl.dt, "ext_field": wl.ext_field,
-                   "precision": head["precision"], "search": head["guess"]},
+                   "precision": head["precision"], "search": head["spec"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": traffic,
-                     "kernel": "pair_fp64_kernel (plain FP64 path)",
-                     "flops_per_pair": plain["flops_per_pair"], "launch_ms": plain["pair_kernel_ms"],
+                     "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": tplain,
+                     "kernel": "pair_fp64_kernel (plain FP64 path, the paper's bisection)",
+                     "flops_per_pair": ROOFLINE_FLOP_PER_PAIR, "counted_flops_per_pair": plain["flops_per_pair"],
+                     "launch_ms": plain["pair_kernel_ms"],
                      # counted HBM bytes over the measured launch time, against 8 TB/s
-                     "hbm_gbs": traffic / (plain["pair_kernel_ms"] * 1e-3) / 1e9 if traffic else None,
-                     "hbm_frac": traffic / (plain["pair_kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS if traffic else None,
-                     "hbm_bytes_per_pair": traffic / (n * (n - 1)) if traffic else None},
-        # the metric's comparison: FP32 + surrogate over the plain FP64 path
+                     "hbm_gbs": tplain / (plain["pair_kernel_ms"] * 1e-3) / 1e9 if tplain else None,
+                     "hbm_frac": tplain / (plain["pair_kernel_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS if tplain else None,
+                     "hbm_bytes_per_pair": tplain / pairs if tplain else None},
+        # the metric's comparison: FP32 + surrogate over the plain FP64 path,
+        # and over the FP64 path with the closed-form straight-line guess
         "speedup_vs_plain_fp64": head["pair_evals_per_s"] / plain["pair_evals_per_s"],
+        "speedup_vs_ballistic": head["pair_evals_per_s"] / ball["pair_evals_per_s"] if ball else None,
         "paths": results,
     }
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(wl, r, u)
+    if c5 and "_fields" in plain:
+        line["error_vs_oracle"] = {"plain": c5_error(plain["_fields"])}
+    if c5 and "stage2" in head:
+        line["stage2"] = head.pop("stage2")
+    if not args.no_cpu and not c5:
+        rec, ref = cpu_baseline(wl, r, u)
+        line["cpu_baseline"] = rec
+        line["error_vs_oracle"] = {x["spec"]: error_vs_oracle(x["_fields"], ref) for x in results if "_fields" in x}
+        log(f"  errors vs the oracle: {line['error_vs_oracle']}")
+    for x in results:
+        x.pop("_fields", None)
     print(json.dumps(line), flush=True)
 
 

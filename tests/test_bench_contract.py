@@ -8,6 +8,7 @@ import json
 import os
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -17,10 +18,16 @@ import bench  # noqa: E402
 from paper_2605_05543_amd import bunch  # noqa: E402
 
 
-def _fake_path(wl, r, u, precision, guess, *args):
-    return {"precision": ["fp64", "mixed"][precision], "guess": bench.GUESS_NAMES[guess],
-            "pair_evals_per_s": [1.2e11, 1.3e11][precision], "ms_per_step": [35.7, 32.9][precision],
-            "pair_kernel_ms": 35.5, "flops_per_pair": 182.9}
+def _fake_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_log2=0, keep_fields=False,
+               stage2=None):
+    spec = f"{['fp64', 'mixed'][precision]}:{bench.GUESS_NAMES[guess]}" + (f"/{group_log2}" if group_log2 else "")
+    rate = {"fp64:bisect": 1.2e11, "fp64:ballistic": 1.35e11}.get(spec, 1.3e11)
+    out = {"precision": ["fp64", "mixed"][precision], "guess": bench.GUESS_NAMES[guess], "spec": spec,
+           "pair_evals_per_s": rate, "ms_per_step": 35.7, "pair_kernel_ms": 35.5, "flops_per_pair": 182.9}
+    if keep_fields:
+        n = wl.bunch.n
+        out["_fields"] = (np.ones((3, n)), np.ones((3, n)))
+    return out
 
 
 def _run_main(monkeypatch, argv):
@@ -38,7 +45,7 @@ def _run_main(monkeypatch, argv):
 
 
 def test_line_has_the_contract_fields(monkeypatch):
-    d = _run_main(monkeypatch, ["--no-cpu", "--paths", "fp64:bisect,mixed:mlp/12"])
+    d = _run_main(monkeypatch, ["--no-cpu", "--paths", "fp64:bisect,mixed:mlp/12,fp64:ballistic"])
     for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
                 "scaling", "vs_baseline", "dtype", "data", "config", "roofline"):
         assert key in d, key
@@ -46,12 +53,16 @@ def test_line_has_the_contract_fields(monkeypatch):
     assert d["config"]["workload"] == bunch.C3.name
     assert d["value"] == 1.3e11  # the FP32 + surrogate path is the headline
     assert abs(d["speedup_vs_plain_fp64"] - 1.3 / 1.2) < 1e-12
+    assert abs(d["speedup_vs_ballistic"] - 1.3 / 1.35) < 1e-12
+    assert d["config"]["search"] == "mixed:mlp/12"
     rf = d["roofline"]
     for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert key in rf, key
     assert rf["bound"] == "alu" and rf["unit"] == "TFLOP/s" and rf["peak"] == 78.6
     n = bunch.C3.bunch.n
-    assert abs(rf["achieved"] - 182.9 * n * (n - 1) / 35.5e-3 / 1e12) < 1e-9
+    # the plan's algorithmic work per pair, over the plain kernel's launch time
+    assert rf["flops_per_pair"] == 220.0 and rf["counted_flops_per_pair"] == 182.9
+    assert abs(rf["achieved"] - 220.0 * n * (n - 1) / 35.5e-3 / 1e12) < 1e-9
     assert abs(rf["frac"] - rf["achieved"] / 78.6) < 1e-12
     # traffic comes from the committed counters while the kernel sources match them
     if rf["traffic"] is not None:
@@ -68,7 +79,25 @@ def test_several_gpus_are_refused(monkeypatch):
 def test_cpu_baseline_record():
     wl = bunch.C1
     r, u = bunch.gaussian_bunch(wl.bunch)
-    rec = bench.cpu_baseline(wl, r, u, target_seconds=0.2)
+    rec, (sub, E, B, SE, SB) = bench.cpu_baseline(wl, r, u, target_seconds=0.2)
     assert rec["kind"] == "oracle" and rec["unit"] == "pair-evals/s"
     assert rec["value"] > 0 and rec["single_core_value"] > 0 and rec["cores"] >= 1
     assert "targets" in rec["sample"] and "one thread" in rec["single_core_sample"]
+    assert E.shape == (3, len(sub)) and np.all(SE > 0)
+    # a path's error against those oracle fields: zero for the oracle's own
+    full = (np.zeros((3, wl.bunch.n)), np.zeros((3, wl.bunch.n)))
+    full[0][:, sub], full[1][:, sub] = E, B
+    err = bench.error_vs_oracle(full, (sub, E, B, SE, SB))
+    assert err["E_max_over_rms"] == 0.0 and err["B_max_over_S"] == 0.0 and err["targets"] == len(sub)
+
+
+def test_headline_error_reported(monkeypatch):
+    """With the oracle leg, the line carries each kept path's field error
+    against the oracle's fields at the baseline's targets."""
+    monkeypatch.setattr(bench, "cpu_baseline", lambda wl, r, u: (
+        {"value": 1.0, "unit": "pair-evals/s", "cores": 1, "kind": "oracle", "sample": "s"},
+        (np.arange(4), np.ones((3, 4)), np.ones((3, 4)), np.ones(4), np.ones(4))))
+    d = _run_main(monkeypatch, ["--paths", "fp64:bisect,mixed:mlp/12"])
+    assert set(d["error_vs_oracle"]) == {"fp64:bisect", "mixed:mlp/12"}
+    assert d["error_vs_oracle"]["mixed:mlp/12"]["E_max_over_rms"] == 0.0
+    assert "_fields" not in json.dumps(d)

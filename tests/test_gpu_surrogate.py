@@ -150,7 +150,8 @@ def test_guess_never_changes_results(precision):
 
 def test_what_the_network_gains():
     """C3 workload (N=65536, D=512, dipole): the network trained on pairs from
-    C2 and C3 bunches against the method without it.  Iterations (sign
+    C2 and C3 bunches against the method without it and against the
+    straight-line control.  Iterations (sign
     tests per pair) over 1024 seeded targets x all sources for the paper's
     bisection, the network evaluated per pair, the network amortised over
     groups of 64 targets (its correction to the straight-line delay at the
@@ -193,6 +194,13 @@ def test_what_the_network_gains():
     assert rep["loss_last"] < 0.05 * rep["loss_first"]
     assert out["mlp-pair"][3] < 0.5 * out["bisect"][3]
     assert out["mlp-group"][3] < 0.5 * out["bisect"][3]
+    # against the straight-line control (the model with z = 0): the C3
+    # histories are straight to within a slot, so the closed form already
+    # places the bracket and the network can only match it, not beat it
+    for name in ("mlp-pair", "mlp-group"):
+        ratio = out[name][3] / out["ballistic"][3]
+        print(f"   {name} / straight line: {ratio:.4f} sign tests", flush=True)
+        assert 0.98 < ratio < 1.02, (name, ratio)
 
 
 @pytest.mark.parametrize("group_log2", [6, 10])
