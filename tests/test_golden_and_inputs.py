@@ -119,3 +119,32 @@ def test_c5_subset_fixture_is_current():
     for a, j, k, alt in doc["near_ties"]:
         assert 0 <= a < 1024 and 0 <= j < n and abs(k - alt) == 1 or {k, alt} == {-1, depth - 1}
     assert 0.3 < doc["before_history_fraction"] < 0.7
+
+
+def test_c2_steps_fixture_is_current():
+    """The stored free run of the N=8192, D=512 workload (oracle positions,
+    momenta, fields and bracket hashes at steps 1 and 10 for 64 seeded
+    targets) was written by the current oracle source for the targets the
+    seeded generator draws today."""
+    import hashlib
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    doc = json.load(open(os.path.join(root, "tests", "golden", "c2_steps.json")))
+    sha = hashlib.sha256(open(os.path.join(root, "oracle", "empp_oracle.c"), "rb").read()).hexdigest()
+    assert doc["oracle_sha256"] == sha, "oracle changed: rerun tests/golden/make_c2_steps.py"
+    wl = bunch.C2
+    assert doc["targets"] == bunch.target_subset(wl.bunch.n, 64, 102).tolist()
+    assert sorted(int(s) for s in doc["steps"]) == [1, 10]
+    for s, e in doc["steps"].items():
+        assert e["t"] == int(s) * wl.dt
+        for key in ("y", "u", "E", "B"):
+            a = np.asarray(e[key])
+            assert a.shape == (3, 64) and np.all(np.isfinite(a))
+        assert np.all(np.asarray(e["SE"]) > 0) and len(e["kstar_sha256"]) == 64
+        assert np.all(np.linalg.norm(e["E"], axis=0) <= np.asarray(e["SE"]) * (1 + 1e-12))
+        # the targets drift along z at the 2 MeV speed (beta = 0.979), to
+        # the bunch's 1e-3 energy and angle spreads
+        g = float(bunch.gamma_of_kinetic(2.0 * bunch.MEV))
+        drift = np.sqrt(1.0 - 1.0 / g**2) * bunch.C_LIGHT * e["t"]
+        z0 = bunch.gaussian_bunch(wl.bunch)[0][2][doc["targets"]]
+        assert abs(np.mean(np.asarray(e["y"][2]) - z0) / drift - 1.0) < 1e-2
