@@ -13,7 +13,7 @@
 // the pair field evaluated.  Targets are visited in a spatial (Morton) order so that
 // the lanes of a wavefront probe nearby history slots.  Sums are kept per
 // target in registers: a plain partial merged into a compensated total
-// (Neumaier in FP64 every 16 sources, Knuth's two-sum in FP32 every 4);
+// (Neumaier in FP64 every 32 sources, Knuth's two-sum in FP32 every 4);
 // source chunks (grid.y) write (sum, compensation) partials that the push
 // kernel merges in a fixed order, so results do not depend on scheduling.
 //
@@ -306,7 +306,7 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     using Real = std::conditional_t<MIX, float, double>;
     Real sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
     Real acc[6] = {0, 0, 0, 0, 0, 0};
-    constexpr int kPlainRun = MIX ? 4 : 16;  // sources per plain partial
+    constexpr int kPlainRun = MIX ? 4 : 32;  // sources per plain partial
     const float kqf = (float)p.kq;
     int groups_in_acc = 0;
     int probes = 0, nbefore = 0, npairs = 0, nfall = 0, nresc = 0;
@@ -507,8 +507,10 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
                 d0y[s] = ry - wn.y;
                 d0z[s] = rz - wn.z;
                 R0[s] = offset_sq(d0x[s], d0y[s], d0z[s]);
-                // a target on the source's present position: eta = 0
-                if (valid[s] && d0x[s] == 0.0 && d0y[s] == 0.0 && d0z[s] == 0.0) {
+                // a target on the source's present position: eta = 0 (one
+                // compare: |d0|^2 is 0 only when d0 is, for offsets above
+                // 1e-154 m)
+                if (valid[s] && R0[s] == 0.0) {
                     fail_j = min(fail_j, (int32_t)jj[s]);
                     valid[s] = false;
                 }
