@@ -313,7 +313,12 @@ empp_status empp_surrogate_forward(empp_ctx *ctx, const float *X, int64_t count,
 empp_status empp_surrogate_loss_grad(empp_ctx *ctx, const float *X, const float *y, int64_t count, double *loss,
                                      float *grad);
 /* Adam training on device rows (X_dev[count][10], y_dev[count]), cycling
- * through them in order, batch rows per step.  Synchronous.              */
+ * through them in order, batch rows per step.  Each optimizer step (forward
+ * and backward on the matrix cores, the fixed-order sum of the block
+ * partials, Adam, the packed bf16 copy) runs inside one cooperative launch
+ * that takes up to 256 steps; results do not depend on scheduling.
+ * Synchronous.  EMPP_EDEVICE if a grid-wide barrier of that launch timed
+ * out (the parameters are then not to be trusted).                      */
 empp_status empp_surrogate_train(empp_ctx *ctx, const float *X_dev, const float *y_dev, int64_t count,
                                  const empp_train_cfg *cfg, empp_train_report *out);
 

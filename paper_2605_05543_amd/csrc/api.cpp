@@ -37,11 +37,9 @@ hipError_t launch_handoff(const double4 *ring_w, int D, int head, double4 *pos, 
                           hipStream_t s);
 hipError_t launch_transport(const TransportParams &p, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpPacked *net, const float *X, int64_t n, float *z, hipStream_t s);
-hipError_t launch_mlp_train(const MlpPacked *net, const float *X, const float *y, int64_t n, float scale,
-                            float *part, int nblocks, hipStream_t s);
-hipError_t launch_mlp_reduce(const float *part, int nblocks, float *grad, hipStream_t s);
-hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *grad, int64_t step, float lr,
-                           hipStream_t s);
+hipError_t mlp_train_max_blocks(int device, int *out);
+hipError_t launch_mlp_sync_clear(unsigned long long *sync, unsigned int *fail, hipStream_t s);
+hipError_t launch_mlp_train(const TrainRun *run, int nblocks, hipStream_t s);
 hipError_t launch_mlp_pack(const float *master, MlpPacked *net, hipStream_t s);
 hipError_t launch_mlp_sample(const SampleParams &p, const int64_t *tgt, const int64_t *src, int64_t count, float *X,
                              float *y, hipStream_t s);
@@ -280,7 +278,11 @@ struct empp_ctx {
         MlpPacked *net = nullptr;
         float *G = nullptr;
         double3 *cent = nullptr, *cent_big = nullptr;
+        unsigned long long *sync = nullptr;  // training barrier arrivals
+        unsigned int *sync_fail = nullptr;
+        float *loss_first = nullptr;
         int part_blocks = 512;
+        int train_blocks = 0;  // resident blocks of the training step
         int64_t adam_step = 0;
         double sigma_ref = 0.0;
         bool ready = false;
@@ -587,7 +589,8 @@ void empp_destroy(empp_ctx *ctx)
         (void)hipEventDestroy(e);
     for (void *p : {(void *)ctx->sg.master, (void *)ctx->sg.m, (void *)ctx->sg.v, (void *)ctx->sg.grad,
                     (void *)ctx->sg.part, (void *)ctx->sg.net, (void *)ctx->sg.G, (void *)ctx->sg.cent,
-                    (void *)ctx->sg.cent_big})
+                    (void *)ctx->sg.cent_big, (void *)ctx->sg.sync, (void *)ctx->sg.sync_fail,
+                    (void *)ctx->sg.loss_first})
         if (p)
             (void)hipFree(p);
     if (ctx->owns_ws && ctx->ws)
@@ -1205,17 +1208,26 @@ static empp_status surrogate_alloc(empp_ctx *ctx)
         {(void **)&ctx->sg.m, kParams * sizeof(float)},
         {(void **)&ctx->sg.v, kParams * sizeof(float)},
         {(void **)&ctx->sg.grad, (kParams + 1) * sizeof(float)},
-        {(void **)&ctx->sg.part, (size_t)ctx->sg.part_blocks * (kParams + 1) * sizeof(float)},
+        {(void **)&ctx->sg.part, (size_t)ctx->sg.part_blocks * kPartStride * sizeof(float)},
         {(void **)&ctx->sg.net, sizeof(MlpPacked)},
         {(void **)&ctx->sg.G, (size_t)ng * N * sizeof(float)},
         {(void **)&ctx->sg.cent, (size_t)ng * sizeof(double3)},
         {(void **)&ctx->sg.cent_big, (size_t)ng * sizeof(double3)},
+        {(void **)&ctx->sg.sync, (size_t)kSyncLine * (kSyncMaxBlocks + 1) * sizeof(unsigned long long)},
+        {(void **)&ctx->sg.sync_fail, sizeof(unsigned int)},
+        {(void **)&ctx->sg.loss_first, sizeof(float)},
     };
     for (auto &w : want) {
         hipError_t e = hipMalloc(w.p, w.bytes);
         if (e != hipSuccess)
             return fail(EMPP_ENOMEM, "hipMalloc(%zu) for the surrogate failed: %s", w.bytes, hipGetErrorString(e));
     }
+    int dev = 0, nb = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(mlp_train_max_blocks(dev, &nb));
+    if (nb < 1)
+        return fail(EMPP_EDEVICE, "the training step does not fit on the device");
+    ctx->sg.train_blocks = std::min(std::min(nb, ctx->sg.part_blocks), kSyncMaxBlocks);
     return EMPP_OK;
 }
 
@@ -1362,16 +1374,64 @@ empp_status empp_surrogate_forward(empp_ctx *ctx, const float *X, int64_t count,
     return st;
 }
 
-// One gradient evaluation on device rows: partial gradients per block,
-// then their fixed-order sum into sg.grad ([kParams] gradient, then the
-// sum of squared residuals).
-static hipError_t surrogate_grad(empp_ctx *ctx, const float *X, const float *y, int64_t count)
+// Training on device rows: per optimizer step, partial gradients per
+// block, their fixed-order sum into sg.grad ([kParams] gradient, then the
+// sum of squared residuals) and, with apply, the Adam update of the masters
+// and the packed network; kStepsPerLaunch steps per cooperative launch.
+// apply = 0: one gradient evaluation of rows X[count] (batch = count).
+// Synchronous; a grid-barrier wait that gave up is an error.
+static empp_status surrogate_run(empp_ctx *ctx, const float *X, const float *y, int64_t count, int64_t batch,
+                                 int64_t steps, double lr, double lr_final, int apply)
 {
-    int nb = (int)std::min<int64_t>(ctx->sg.part_blocks, (count + 63) / 64);
-    hipError_t e = launch_mlp_train(ctx->sg.net, X, y, count, 2.0f / (float)count, ctx->sg.part, nb, ctx->stream);
-    if (e == hipSuccess)
-        e = launch_mlp_reduce(ctx->sg.part, nb, ctx->sg.grad, ctx->stream);
-    return e;
+    constexpr int64_t kStepsPerLaunch = 256;
+    const int nb = (int)std::min<int64_t>(ctx->sg.train_blocks, (batch + 63) / 64);
+    const int64_t nl = (steps + kStepsPerLaunch - 1) / kStepsPerLaunch;
+    std::vector<TrainRun> runs((size_t)nl);
+    unsigned long long arrivals = 0;
+    for (int64_t k = 0; k < nl; ++k) {
+        TrainRun &r = runs[(size_t)k];
+        r.net = ctx->sg.net;
+        r.X = X;
+        r.y = y;
+        r.count = count;
+        r.batch = (int32_t)batch;
+        r.step0 = k * kStepsPerLaunch;
+        r.steps = (int32_t)std::min(kStepsPerLaunch, steps - r.step0);
+        r.total = steps;
+        r.adam0 = ctx->sg.adam_step + r.step0;
+        r.lr = lr;
+        r.lr_final = lr_final;
+        r.apply = apply;
+        r.part = ctx->sg.part;
+        r.grad = ctx->sg.grad;
+        r.master = ctx->sg.master;
+        r.m = ctx->sg.m;
+        r.v = ctx->sg.v;
+        r.loss_first = ctx->sg.loss_first;
+        r.sync = ctx->sg.sync;
+        r.sync_base = arrivals;
+        r.fail = ctx->sg.sync_fail;
+        arrivals += (unsigned long long)nb * (unsigned long long)(2 * r.steps - 1);
+    }
+    TrainRun *dev = nullptr;
+    HIP_TRY(hipMalloc((void **)&dev, (size_t)nl * sizeof(TrainRun)));
+    auto body = [&]() -> empp_status {
+        HIP_TRY(hipMemcpy(dev, runs.data(), (size_t)nl * sizeof(TrainRun), hipMemcpyHostToDevice));
+        HIP_TRY(launch_mlp_sync_clear(ctx->sg.sync, ctx->sg.sync_fail, ctx->stream));
+        for (int64_t k = 0; k < nl; ++k)
+            HIP_TRY(launch_mlp_train(dev + k, nb, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        unsigned int f = 0;
+        HIP_TRY(hipMemcpy(&f, ctx->sg.sync_fail, sizeof(f), hipMemcpyDeviceToHost));
+        if (f)
+            return fail(EMPP_EDEVICE, "a grid barrier of the training kernel timed out");
+        return EMPP_OK;
+    };
+    empp_status st = body();
+    (void)hipFree(dev);
+    if (st == EMPP_OK && apply)
+        ctx->sg.adam_step += steps;
+    return st;
 }
 
 empp_status empp_surrogate_loss_grad(empp_ctx *ctx, const float *X, const float *y, int64_t count, double *loss,
@@ -1380,7 +1440,7 @@ empp_status empp_surrogate_loss_grad(empp_ctx *ctx, const float *X, const float 
     empp_status st = surrogate_precheck(ctx, false);
     if (st != EMPP_OK)
         return st;
-    if (count <= 0 || !X || !y || !grad)
+    if (count <= 0 || count > (int64_t)INT32_MAX || !X || !y || !grad)
         return fail(EMPP_EINVAL, "bad arguments");
     float *tmp = nullptr;
     HIP_TRY(hipMalloc((void **)&tmp, (size_t)count * (kIn + 1) * sizeof(float)));
@@ -1388,10 +1448,11 @@ empp_status empp_surrogate_loss_grad(empp_ctx *ctx, const float *X, const float 
     auto body = [&]() -> empp_status {
         HIP_TRY(hipMemcpyAsync(tmp, X, count * kIn * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
         HIP_TRY(hipMemcpyAsync(tmp + count * kIn, y, count * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
-        HIP_TRY(surrogate_grad(ctx, tmp, tmp + count * kIn, count));
-        HIP_TRY(hipMemcpyAsync(g.data(), ctx->sg.grad, (kParams + 1) * sizeof(float), hipMemcpyDeviceToHost,
-                               ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
+        empp_status s2 = surrogate_run(ctx, tmp, tmp + count * kIn, count, count, 1, 0.0, 0.0, 0);
+        if (s2 != EMPP_OK)
+            return s2;
+        HIP_TRY(hipMemcpy(g.data(), ctx->sg.grad, (kParams + 1) * sizeof(float), hipMemcpyDeviceToHost));
         return EMPP_OK;
     };
     st = body();
@@ -1417,25 +1478,13 @@ empp_status empp_surrogate_train(empp_ctx *ctx, const float *X_dev, const float 
     auto t0 = std::chrono::steady_clock::now();
     float first = 0.0f, last = 0.0f;
     const int64_t B = cfg->batch;
-    for (int64_t s = 0; s < cfg->steps; ++s) {
-        int64_t start = (s * B) % count;
-        if (start + B > count)
-            start = 0;
-        HIP_TRY(surrogate_grad(ctx, X_dev + start * kIn, y_dev + start, B));
-        if (s == 0) {
-            HIP_TRY(hipMemcpyAsync(&first, ctx->sg.grad + kParams, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-        }
-        if (s == cfg->steps - 1) {
-            HIP_TRY(hipMemcpyAsync(&last, ctx->sg.grad + kParams, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-        }
-        double frac = cfg->steps > 1 ? (double)s / (double)(cfg->steps - 1) : 1.0;
-        float lr = (float)(cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) * (1.0 + std::cos(M_PI * frac)));
-        ctx->sg.adam_step += 1;
-        HIP_TRY(launch_mlp_adam(ctx->sg.master, ctx->sg.m, ctx->sg.v, ctx->sg.grad, ctx->sg.adam_step, lr,
-                                ctx->stream));
-        HIP_TRY(launch_mlp_pack(ctx->sg.master, ctx->sg.net, ctx->stream));
+    if (cfg->steps > 0) {
+        if ((st = surrogate_run(ctx, X_dev, y_dev, count, B, cfg->steps, (double)cfg->lr, (double)cfg->lr_final, 1)) !=
+            EMPP_OK)
+            return st;
+        HIP_TRY(hipMemcpy(&first, ctx->sg.loss_first, sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&last, ctx->sg.grad + kParams, sizeof(float), hipMemcpyDeviceToHost));
     }
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
     auto t1 = std::chrono::steady_clock::now();
     if (out) {
         out->loss_first = (double)first / (double)B;

@@ -1,8 +1,10 @@
 // mlp.hip -- the retarded-delay surrogate network 10 -> 128 -> 128 -> 1
 // (SiLU hidden layers) with BF16 weights and activations on the matrix
-// cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation): inference, training
-// (forward + backward + Adam) and the sampling of training pairs from the
-// stored histories.
+// cores, FP32 accumulation: the 10-input layer on v_mfma_f32_16x16x16_bf16,
+// every 128-deep product (layer 2, its backward, the weight gradients) on
+// gfx950's v_mfma_f32_16x16x32_bf16.  Inference, training (forward,
+// backward, the fixed-order gradient sum and Adam in one launch per
+// optimizer step) and the sampling of training pairs from the histories.
 //
 // The model predicts the normalised retarded delay g = c (t - t_r) /
 // |r - w_n| of a (target, source) pair as g_line exp(z): g_line is the
@@ -14,13 +16,18 @@
 //
 // Layout of the flat parameter vector (FP32 masters, 18049 values):
 //   W1[128][10], b1[128], W2[128][128], b2[128], W3[1][128], b3[1].
-// Matrix-core layout used throughout (checked on gfx950): for
-// D = A B with A 16x16 (M x K), B 16x16 (K x N), lane l holds
-//   A[l % 16][4 (l / 16) + r], B[4 (l / 16) + r][l % 16],
-//   D[4 (l / 16) + r][l % 16],  r = 0..3.
+// Matrix-core layouts used throughout (checked on gfx950): for D = A B,
+// lane l, lane group g = l / 16,
+//   16x16x16: A[l % 16][4 g + r], B[4 g + r][l % 16], r = 0..3;
+//   16x16x32: A[l % 16][s(g, r)], B[s(g, r)][l % 16], r = 0..7, where the
+//             pairing of A and B slots is the only thing the sum needs;
+//   both:     D[4 g + r][l % 16], r = 0..3.
 // Layers are evaluated transposed, H^T = W X^T, so the D layout of one
-// layer is exactly the B layout the next layer needs: activations stay in
-// registers between layers.
+// layer is the B layout of the next: activations stay in registers.  Two
+// D tiles (rows 0..15 and 16..31 of a 32-deep block) give lane group g the
+// rows 4 g + r and 16 + 4 g + r: that is the slot order s(g, r) of every
+// 16x16x32 product here, and weight rows are stored with their columns in
+// that order, so one 16-byte LDS read gives a lane its 8 A values.
 #include "empp_dev.h"
 #include "mlp_dev.h"
 #include "pair_common.h"
@@ -30,9 +37,17 @@ namespace empp {
 namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f4 mfma16(s4 a, s4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ f4 mfma32(s8 a, s8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+// the 8 K values of a lane: 4 from each of two 16-deep halves
+__device__ __forceinline__ s8 cat(s4 lo, s4 hi) { return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7); }
 
 // Round to the nearest bfloat16, ties to even (finite inputs).
 __device__ __forceinline__ unsigned short bf16_bits(float f)
@@ -57,34 +72,58 @@ __device__ __forceinline__ float silu_grad(float x)
 }
 
 // Network weights staged in LDS: W1 [128][16] (K padded, column 10 is 0),
-// W2 [128][128], the bf16-rounded biases and W3 as floats.  Rows are padded
-// (to 20 and 132 halfwords) so that the 16 rows one A-fragment read touches
-// start on distinct banks.
-constexpr int kW1S = 20, kW2S = 132;
+// W2 [128][128] (columns in slot order), the bf16-rounded biases and W3 as
+// floats.  Rows are padded so that the 16 rows one A-fragment read touches
+// start on distinct banks: 20 halfwords for the 8-byte reads of W1, 136
+// (68 dwords, 4 mod 32) for the 16-byte reads of W2, which put 8 lanes on
+// 8 disjoint groups of 4 banks.
+constexpr int kW1S = 20, kW2S = 136;
 struct NetLds {
     unsigned short W1[kHid * kW1S];
-    unsigned short W2[kHid * kW2S];
+    alignas(16) unsigned short W2[kHid * kW2S];
     float b1[kHid], b2[kHid], W3[kHid], b3;
 };
 
+// Every network kernel runs 256-thread blocks.
+constexpr int kMlpThreads = 256;
+
+// A [128][128] bf16 matrix from global memory into LDS rows of kW2S
+// halfwords, eight halfwords per copy.
+__device__ __forceinline__ void load_matrix(unsigned short *dst, const unsigned short *src)
+{
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+    for (int k = 0; k < kHid * kHid / 8 / kMlpThreads; ++k) {
+        const int i = threadIdx.x + k * kMlpThreads;
+        d4[(i / (kHid / 8)) * (kW2S / 8) + i % (kHid / 8)] = s4[i];
+    }
+}
+
 __device__ void load_net(NetLds &s, const MlpPacked *net)
 {
-    // two halfwords per copy; rows keep their padded stride
+    // two halfwords per copy for W1; rows keep their padded stride
     const uint32_t *src1 = reinterpret_cast<const uint32_t *>(net->W1);
     uint32_t *dst1 = reinterpret_cast<uint32_t *>(s.W1);
-    for (int i = threadIdx.x; i < kHid * 16 / 2; i += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < kHid * 16 / 2 / kMlpThreads; ++k) {
+        const int i = threadIdx.x + k * kMlpThreads;
         dst1[(i / 8) * (kW1S / 2) + i % 8] = src1[i];
-    const uint32_t *src2 = reinterpret_cast<const uint32_t *>(net->W2);
-    uint32_t *dst2 = reinterpret_cast<uint32_t *>(s.W2);
-    for (int i = threadIdx.x; i < kHid * kHid / 2; i += blockDim.x)
-        dst2[(i / (kHid / 2)) * (kW2S / 2) + i % (kHid / 2)] = src2[i];
-    for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
+    }
+    load_matrix(s.W2, net->W2);
+    if (threadIdx.x < kHid) {
+        const int i = threadIdx.x;
         s.b1[i] = net->b1[i];
         s.b2[i] = net->b2[i];
         s.W3[i] = net->W3[i];
     }
     if (threadIdx.x == 0)
         s.b3 = net->b3;
+}
+
+__device__ __forceinline__ s8 lds_s8(const unsigned short *p)
+{
+    return __builtin_bit_cast(s8, *reinterpret_cast<const uint4 *>(p));
 }
 
 __device__ __forceinline__ s4 lds_s4(const unsigned short *p)
@@ -117,12 +156,12 @@ __device__ __forceinline__ s4 pack4(float a, float b, float c, float d)
 
 // Forward pass of 16 rows held by one wavefront.  x4: the 4 features
 // 4 (l/16) .. 4 (l/16) + 3 of row l % 16 (zero beyond 10).  Returns z of
-// row l % 16 (valid in every lane).  Optionally keeps the pre-activations
-// and bf16 activations for the backward pass.
+// row l % 16 (valid in every lane).  For training (KEEP) it keeps the
+// pre-activations in registers and writes the bf16 activations H1^T and
+// H2^T ([unit][row], 16 rows) to the wavefront's LDS tiles.
 struct FwdState {
-    f4 a1[8], a2[8];  // pre-activations (D layout)
-    s4 h1[8];         // bf16 H1^T tiles (B layout of layer 2)
-    f4 h2[8];         // H2^T (float)
+    f4 a1[8], a2[8];            // pre-activations (D layout)
+    unsigned short *h1t, *h2t;  // LDS tiles of H1^T, H2^T
 };
 
 template <bool KEEP>
@@ -145,17 +184,20 @@ __device__ __forceinline__ float net_forward(const NetLds &s, s4 xb, FwdState &s
             v[r] = KEEP ? silu(pre) : silu_fast(pre);
         }
         h1[mt] = pack4(v[0], v[1], v[2], v[3]);
-        if (KEEP)
-            st.h1[mt] = h1[mt];
+        if (KEEP) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                st.h1t[(mt * 16 + 4 * g + r) * 16 + col] = (unsigned short)h1[mt][r];
+        }
     }
     // layer 2: H2^T = W2 H1^T
     float z = 0.0f;
     auto tile2 = [&](int mt) {
         f4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int kt = 0; kt < 8; ++kt) {
-            s4 a = lds_s4(&s.W2[(mt * 16 + col) * kW2S + kt * 16 + 4 * g]);
-            acc = mfma16(a, h1[kt], acc);
+        for (int kt = 0; kt < 4; ++kt) {
+            s8 a = lds_s8(&s.W2[(mt * 16 + col) * kW2S + kt * 32 + 8 * g]);
+            acc = mfma32(a, cat(h1[2 * kt], h1[2 * kt + 1]), acc);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -164,7 +206,7 @@ __device__ __forceinline__ float net_forward(const NetLds &s, s4 xb, FwdState &s
             float h = KEEP ? silu(pre) : silu_fast(pre);
             if (KEEP) {
                 st.a2[mt][r] = pre;
-                st.h2[mt][r] = h;
+                st.h2t[j * 16 + col] = bf16_bits(h);
             }
             z += s.W3[j] * h;
         }
@@ -232,11 +274,11 @@ __device__ __forceinline__ void net_forward_tiles(const NetLds &s, const s4 xb[T
         for (int t = 0; t < T; ++t)
             acc[t] = f4{0, 0, 0, 0};
 #pragma unroll
-        for (int kt = 0; kt < 8; ++kt) {
-            s4 a = lds_s4(&s.W2[(mt * 16 + col) * kW2S + kt * 16 + 4 * g]);
+        for (int kt = 0; kt < 4; ++kt) {
+            s8 a = lds_s8(&s.W2[(mt * 16 + col) * kW2S + kt * 32 + 8 * g]);
 #pragma unroll
             for (int t = 0; t < T; ++t)
-                acc[t] = mfma16(a, h1[t][kt], acc[t]);
+                acc[t] = mfma32(a, cat(h1[t][2 * kt], h1[t][2 * kt + 1]), acc[t]);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -279,34 +321,44 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const MlpPacked *net, 
 }
 
 // ---------------------------------------------------------------------------
-// Training step part 1: forward + backward of every row, gradients of the
-// mean squared error of z against y accumulated per block (matrix cores for
-// every product, biases through an appended column of ones), written as
-// one partial gradient per block.  part[block][kParams + 1]: the flat
-// gradient and the block's sum of squared residuals.
+// Training, many optimizer steps per launch.  Phase 1: forward + backward
+// of every row, gradients of the mean squared error of z against y
+// accumulated per block (matrix cores for every product, biases through
+// an appended column of ones), written as one partial gradient per block:
+// part[block][kPartStride], the flat gradient and the block's sum of
+// squared residuals.  Phase 2, after a grid-wide barrier (the launch is
+// cooperative, so every block is resident): each parameter's partials are
+// summed in a fixed order (FP64, so the result does not depend on
+// scheduling), then Adam (bias-corrected) updates the FP32 master and the
+// packed bf16 copy the next step's forward pass reads.
 struct TrainLds {
     NetLds net;
-    unsigned short W2T[kHid * kHid];       // W2 transposed
-    unsigned short H1T[4][kHid * 16];      // per wave: H1^T [j][i]
-    unsigned short dA2T[4][kHid * 16];     // dA2^T [j][i]
-    unsigned short dA1T[4][kHid * 16];     // dA1^T [j][i]
-    unsigned short H2T[4][kHid * 16];      // H2^T [j][i]
-    unsigned short XeT[4][16 * 16];        // [X | 1]^T [k][i] (column 10 of X is 1)
-    unsigned short dzT[4][16 * 16];        // [dz | 0]^T [k][i] (k = 0: dz_i)
+    alignas(16) unsigned short W2T[kHid * kW2S];  // W2 transposed (columns in slot order)
+    unsigned short H1T[4][kHid * 16];              // per wave: H1^T [j][i]
+    unsigned short dA2T[4][kHid * 16];             // dA2^T [j][i]
+    unsigned short dA1T[4][kHid * 16];             // dA1^T [j][i]
+    unsigned short H2T[4][kHid * 16];              // H2^T [j][i]
+    unsigned short XeT[4][16 * 16];                // [X | 1]^T [k][i] (column 10 of X is 1)
+    unsigned short dzT[4][16 * 16];                // [dz | 0]^T [k][i] (k = 0: dz_i)
 };
 static_assert(sizeof(TrainLds) <= 160 * 1024, "training tile exceeds the 160 KiB of LDS");
 
-__global__ __launch_bounds__(256) void mlp_train_kernel(const MlpPacked *net, const float *X, const float *y,
-                                                        int64_t n, float scale, float *part)
+// A store that other blocks read after the next grid barrier, written
+// through to device scope, so that the barrier's release has little left
+// in the XCD's L2 to write back.
+template <typename T>
+__device__ __forceinline__ void store_shared(T &dst, T val)
 {
-    extern __shared__ unsigned char tls_raw[];
-    TrainLds &s = *reinterpret_cast<TrainLds *>(tls_raw);
+    __hip_atomic_store(&dst, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Phase 1 for this block's rows X[n][10], y[n] (64 per chunk, chunks
+// strided by the grid): the block's partial gradient into out.
+__device__ void block_gradient(TrainLds &s, const MlpPacked *net, const float *X, const float *y, int64_t n,
+                               float scale, float *out)
+{
     load_net(s.net, net);
-    __syncthreads();
-    for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x) {
-        int m = i / kHid, k = i % kHid;
-        s.W2T[m * kHid + k] = s.net.W2[k * kW2S + m];
-    }
+    load_matrix(s.W2T, net->W2T);
     __syncthreads();
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = l >> 4, col = l & 15;
@@ -330,13 +382,15 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(const MlpPacked *net, co
         for (int k = 0; k < kIn; ++k)
             f[k] = live ? X[row * kIn + k] : 0.0f;
         FwdState st;
+        st.h1t = s.H1T[w];
+        st.h2t = s.H2T[w];
         float z = net_forward<true>(s.net, feature_operand(f), st);
         float res = live ? z - y[row] : 0.0f;
         float dz = live ? scale * res : 0.0f;
         if (l < 16)
             sqsum += res * res;
         gb3 += (l < 16) ? dz : 0.0f;
-        // dA2^T = W3 dz silu'(A2^T); also write H1^T, H2^T, dA2^T (bf16) for the products
+        // dA2^T = W3 dz silu'(A2^T), also written (bf16) for the products
         s4 da2[8];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
@@ -345,22 +399,21 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(const MlpPacked *net, co
             for (int r = 0; r < 4; ++r) {
                 int j = mt * 16 + 4 * g + r;
                 v[r] = s.net.W3[j] * dz * silu_grad(st.a2[mt][r]);
-                s.H2T[w][j * 16 + col] = bf16_bits(st.h2[mt][r]);
-                s.H1T[w][j * 16 + col] = (unsigned short)st.h1[mt][r];
             }
             da2[mt] = pack4(v[0], v[1], v[2], v[3]);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 s.dA2T[w][(mt * 16 + 4 * g + r) * 16 + col] = (unsigned short)da2[mt][r];
         }
-        // dH1^T = W2^T dA2^T; dA1^T = dH1^T silu'(A1^T)
+        // dH1^T = W2^T dA2^T (K = the 128 units of layer 2, slot order);
+        // dA1^T = dH1^T silu'(A1^T)
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
             f4 acc = {0, 0, 0, 0};
 #pragma unroll
-            for (int kt = 0; kt < 8; ++kt) {
-                s4 a = lds_s4(&s.W2T[(mt * 16 + col) * kHid + kt * 16 + 4 * g]);
-                acc = mfma16(a, da2[kt], acc);
+            for (int kt = 0; kt < 4; ++kt) {
+                s8 a = lds_s8(&s.W2T[(mt * 16 + col) * kW2S + kt * 32 + 8 * g]);
+                acc = mfma32(a, cat(da2[2 * kt], da2[2 * kt + 1]), acc);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -375,32 +428,36 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(const MlpPacked *net, co
             s.dzT[w][k * 16 + col] = bf16_bits(k == 0 ? dz : 0.0f);
         }
         __syncthreads();
-        // weight gradients over the block's 64 rows (K = rows)
+        // weight gradients over the block's 64 rows (K = rows, two waves'
+        // 16-row tiles per 32-deep step: slot r < 4 is row 4 g + r of the
+        // first, r >= 4 row 4 g + r - 4 of the second, in A and B alike)
 #pragma unroll
-        for (int ww = 0; ww < 4; ++ww) {
+        for (int pr = 0; pr < 2; ++pr) {
+            const int w0 = 2 * pr, w1 = 2 * pr + 1;
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 const int mt = 2 * w + a;
                 // A: dA2^T rows j, K = rows i;  B: [H1 | 1] rows i, N = units k
-                s4 A2 = lds_s4(&s.dA2T[ww][(mt * 16 + col) * 16 + 4 * g]);
+                const int ra = (mt * 16 + col) * 16 + 4 * g;
+                s8 A2 = cat(lds_s4(&s.dA2T[w0][ra]), lds_s4(&s.dA2T[w1][ra]));
 #pragma unroll
                 for (int nt = 0; nt < 8; ++nt) {
-                    s4 Bh = lds_s4(&s.H1T[ww][(nt * 16 + col) * 16 + 4 * g]);
-                    gW2[a][nt] = mfma16(A2, Bh, gW2[a][nt]);
+                    const int rb = (nt * 16 + col) * 16 + 4 * g;
+                    gW2[a][nt] = mfma32(A2, cat(lds_s4(&s.H1T[w0][rb]), lds_s4(&s.H1T[w1][rb])), gW2[a][nt]);
                 }
                 // ones column (bias gradient): B[i][k] = 1 for k = 0
-                s4 ones = (col == 0) ? pack4(1.0f, 1.0f, 1.0f, 1.0f) : s4{0, 0, 0, 0};
-                gW2[a][8] = mfma16(A2, ones, gW2[a][8]);
-                s4 A1 = lds_s4(&s.dA1T[ww][(mt * 16 + col) * 16 + 4 * g]);
-                gW1[a] = mfma16(A1, lds_s4(&s.XeT[ww][col * 16 + 4 * g]), gW1[a]);
-                s4 H2 = lds_s4(&s.H2T[ww][(mt * 16 + col) * 16 + 4 * g]);
-                gW3[a] = mfma16(H2, lds_s4(&s.dzT[ww][col * 16 + 4 * g]), gW3[a]);
+                const s4 one4 = (col == 0) ? pack4(1.0f, 1.0f, 1.0f, 1.0f) : s4{0, 0, 0, 0};
+                gW2[a][8] = mfma32(A2, cat(one4, one4), gW2[a][8]);
+                s8 A1 = cat(lds_s4(&s.dA1T[w0][ra]), lds_s4(&s.dA1T[w1][ra]));
+                const int rx = col * 16 + 4 * g;
+                gW1[a] = mfma32(A1, cat(lds_s4(&s.XeT[w0][rx]), lds_s4(&s.XeT[w1][rx])), gW1[a]);
+                s8 H2 = cat(lds_s4(&s.H2T[w0][ra]), lds_s4(&s.H2T[w1][ra]));
+                gW3[a] = mfma32(H2, cat(lds_s4(&s.dzT[w0][rx]), lds_s4(&s.dzT[w1][rx])), gW3[a]);
             }
         }
         __syncthreads();
     }
-    // write this block's partial gradient in the flat layout
-    float *out = part + (int64_t)blockIdx.x * (kParams + 1);
+    // this block's partial gradient in the flat layout
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const int mt = 2 * w + a;
@@ -409,15 +466,15 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(const MlpPacked *net, co
             const int j = mt * 16 + 4 * g + r;
 #pragma unroll
             for (int nt = 0; nt < 8; ++nt)
-                out[kOffW2 + j * kHid + nt * 16 + col] = gW2[a][nt][r];
+                store_shared(out[kOffW2 + j * kHid + nt * 16 + col], gW2[a][nt][r]);
             if (col == 0)
-                out[kOffB2 + j] = gW2[a][8][r];
+                store_shared(out[kOffB2 + j], gW2[a][8][r]);
             if (col < kIn)
-                out[kOffW1 + j * kIn + col] = gW1[a][r];
+                store_shared(out[kOffW1 + j * kIn + col], gW1[a][r]);
             if (col == kIn)
-                out[kOffB1 + j] = gW1[a][r];
+                store_shared(out[kOffB1 + j], gW1[a][r]);
             if (col == 0)
-                out[kOffW3 + j] = gW3[a][r];
+                store_shared(out[kOffW3 + j], gW3[a][r]);
         }
     }
     // b3 and the squared residuals: wave sums, then the block's
@@ -432,57 +489,200 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(const MlpPacked *net, co
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        out[kOffB3] = red_b3[0] + red_b3[1] + red_b3[2] + red_b3[3];
-        out[kParams] = red_sq[0] + red_sq[1] + red_sq[2] + red_sq[3];
+        store_shared(out[kOffB3], red_b3[0] + red_b3[1] + red_b3[2] + red_b3[3]);
+        store_shared(out[kParams], red_sq[0] + red_sq[1] + red_sq[2] + red_sq[3]);
     }
 }
 
-// Part 2: sum the block partials in a fixed order.
-__global__ void mlp_reduce_kernel(const float *part, int nblocks, float *grad)
+// Grid-wide barrier of a cooperative launch.  sync[0] counts arrivals;
+// the block that brings it to the target writes the target into every
+// block's flag (sync[kSyncLine (b + 1)], one 128-byte line per block), and
+// each other block waits on its own flag, so no line is polled by more than
+// one block.  Thread 0 of a block carries the block's synchronisation: its
+// arrival releases what the block wrote (the block's threads have finished
+// their stores at the preceding __syncthreads) and acquires what the blocks
+// before it released; the flags are polled with relaxed loads and one
+// acquire fence follows the wait, so the XCD's L2 is invalidated once per
+// barrier, not once per poll.  The wait is bounded (about a second); a block
+// that gives up sets *fail, which the host reports, and goes on, so every
+// wave still ends.
+constexpr unsigned kSyncSpinLimit = 1u << 20;
+__device__ void grid_barrier(unsigned long long *sync, unsigned long long target, unsigned int *fail)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > kParams)
-        return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b)
-        s += part[(int64_t)b * (kParams + 1) + p];
-    grad[p] = (float)s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long seen =
+            __hip_atomic_fetch_add(sync, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        if (seen == target) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (int b = 0; b < (int)gridDim.x; ++b)
+                __hip_atomic_store(&sync[kSyncLine * (b + 1)], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned long long *flag = &sync[kSyncLine * (blockIdx.x + 1)];
+            unsigned spins = 0;
+            while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (++spins > kSyncSpinLimit) {
+                    atomicOr(fail, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+    }
+    __syncthreads();
 }
 
-// Part 3: Adam (bias-corrected) on the FP32 masters, then the bf16 copies.
-__global__ void mlp_adam_kernel(float *master, float *m, float *v, const float *grad, int64_t step, float lr,
-                                float beta1, float beta2, float eps)
+// One parameter of the packed network from its FP32 master value.
+__device__ __forceinline__ void pack_param(MlpPacked *net, int q, float x)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= kParams)
-        return;
-    float gr = grad[p];
-    float mm = beta1 * m[p] + (1.0f - beta1) * gr;
-    float vv = beta2 * v[p] + (1.0f - beta2) * gr * gr;
-    m[p] = mm;
-    v[p] = vv;
-    float mh = mm / (1.0f - powf(beta1, (float)step));
-    float vh = vv / (1.0f - powf(beta2, (float)step));
-    master[p] -= lr * mh / (sqrtf(vh) + eps);
+    if (q < kOffB1) {
+        store_shared(net->W1[(q / kIn) * 16 + q % kIn], bf16_bits(x));
+    } else if (q < kOffW2) {
+        store_shared(net->b1[q - kOffB1], bf16_value(bf16_bits(x)));
+    } else if (q < kOffB2) {
+        const int j = (q - kOffW2) / kHid, k = (q - kOffW2) % kHid;
+        const unsigned short h = bf16_bits(x);
+        store_shared(net->W2[j * kHid + slot_of_col(k)], h);
+        store_shared(net->W2T[k * kHid + slot_of_col(j)], h);
+    } else if (q < kOffW3) {
+        store_shared(net->b2[q - kOffB2], bf16_value(bf16_bits(x)));
+    } else if (q < kOffB3) {
+        store_shared(net->W3[q - kOffW3], bf16_value(bf16_bits(x)));
+    } else {
+        store_shared(net->b3, bf16_value(bf16_bits(x)));
+    }
 }
 
-// FP32 masters -> packed network (bf16 matrices, bf16-rounded vectors).
+// Phase 2 for this block's slice [q0, q1) of the parameters (q0 a
+// multiple of 4): column c of the slice's 16-byte units is summed over the
+// block partials b = r, r + R, ... by thread (c, r), in FP64, and the R
+// sums of a column are then added in order r = 0, 1, ...: a fixed order,
+// whatever the scheduling.  Then the gradient, Adam (bias-corrected) on
+// the FP32 masters and the packed network for those parameters.
+__device__ void reduce_and_update(const TrainRun &p, double4 *red, int q0, int q1, int64_t gs, int it)
+{
+    const int nb = (int)gridDim.x;
+    const double frac = p.total > 1 ? (double)gs / (double)(p.total - 1) : 1.0;
+    const float lr = (float)(p.lr_final + 0.5 * (p.lr - p.lr_final) * (1.0 + cos(M_PI * frac)));
+    const float step = (float)(p.adam0 + it + 1);
+    const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f - powf(beta1, step), c2 = 1.0f - powf(beta2, step);
+    const int ncol = (q1 - q0 + 3) / 4;
+    const int cols = ncol < 64 ? ncol : 64;  // columns per pass
+    const int R = kMlpThreads / cols;         // partial subsets per column
+    const int c = threadIdx.x % cols, r = threadIdx.x / cols;
+    for (int c0 = 0; c0 < ncol; c0 += cols) {
+        const int col = c0 + c;
+        double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (r < R && col < ncol) {
+            const float4 *src = reinterpret_cast<const float4 *>(p.part + q0) + col;
+#pragma unroll 8
+            for (int b = r; b < nb; b += R) {
+                const float4 x = src[(int64_t)b * (kPartStride / 4)];
+                acc.x += x.x;
+                acc.y += x.y;
+                acc.z += x.z;
+                acc.w += x.w;
+            }
+        }
+        if (r < R)
+            red[r * cols + c] = acc;
+        __syncthreads();
+        if (r == 0 && col < ncol) {
+            double4 t = red[c];
+            for (int k = 1; k < R; ++k) {
+                const double4 u = red[k * cols + c];
+                t.x += u.x;
+                t.y += u.y;
+                t.z += u.z;
+                t.w += u.w;
+            }
+            const double tv[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int q = q0 + 4 * col + e;
+                if (q >= q1)
+                    break;
+                const float gr = (float)tv[e];
+                p.grad[q] = gr;
+                if (q == kParams && gs == 0)
+                    *p.loss_first = gr;
+                if (p.apply && q < kParams) {
+                    const float mm = beta1 * p.m[q] + (1.0f - beta1) * gr;
+                    const float vv = beta2 * p.v[q] + (1.0f - beta2) * gr * gr;
+                    p.m[q] = mm;
+                    p.v[q] = vv;
+                    const float x = p.master[q] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+                    p.master[q] = x;
+                    pack_param(p.net, q, x);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Training: p.steps optimizer steps in one launch.  Per step: phase 1 on
+// the step's batch (consecutive rows, wrapping to the start when a batch
+// would run past the end), a grid barrier, phase 2 on this block's slice
+// of the parameters, and a second barrier before the next step reads the
+// packed network.
+__global__ __launch_bounds__(kMlpThreads) void mlp_train_kernel(const TrainRun *run)
+{
+    // The run's parameters are read from device memory where they are used
+    // (the empty asm statements below mark memory as changed, so they are
+    // not held in registers across the step loop, which would spill).
+    const TrainRun &p = *run;
+    extern __shared__ unsigned char tls_raw[];
+    TrainLds &s = *reinterpret_cast<TrainLds *>(tls_raw);
+    // phase 2's column sums reuse the H1^T tiles (16 KiB, 512 double4)
+    static_assert(sizeof(s.H1T) >= kMlpThreads * sizeof(double4), "phase-2 sums fit the H1^T tiles");
+    double4 *red = reinterpret_cast<double4 *>(&s.H1T[0][0]);
+    const int nb = (int)gridDim.x;
+    const int slice = ((kParams + 1 + nb - 1) / nb + 3) & ~3;
+    const int q0 = min((int)blockIdx.x * slice, kParams + 1);
+    const int q1 = min(q0 + slice, kParams + 1);
+    unsigned long long target = p.sync_base;
+    for (int it = 0; it < p.steps; ++it) {
+        asm volatile("" ::: "memory");
+        const int64_t gs = p.step0 + it;
+        int64_t start = (gs * p.batch) % p.count;
+        if (start + p.batch > p.count)
+            start = 0;
+        block_gradient(s, p.net, p.X + start * kIn, p.y + start, p.batch, 2.0f / (float)p.batch,
+                       p.part + (int64_t)blockIdx.x * kPartStride);
+        target += nb;
+        grid_barrier(p.sync, target, p.fail);
+        asm volatile("" ::: "memory");
+        if (q0 < q1)
+            reduce_and_update(p, red, q0, q1, gs, it);
+        if (it + 1 < p.steps) {
+            target += nb;
+            grid_barrier(p.sync, target, p.fail);
+        }
+    }
+}
+
+// Clears the barrier counter, the flags of up to kSyncMaxBlocks blocks and
+// the failure word (one block of kMlpThreads threads).
+__global__ void mlp_sync_clear_kernel(unsigned long long *sync, unsigned int *fail)
+{
+    for (int i = threadIdx.x; i < kSyncLine * (kSyncMaxBlocks + 1); i += blockDim.x)
+        sync[i] = 0;
+    if (threadIdx.x == 0)
+        *fail = 0;
+}
+
+// FP32 masters -> packed network (bf16 matrices, bf16-rounded vectors;
+// the padding columns of W1 are zero).
 __global__ void mlp_pack_kernel(const float *master, MlpPacked *net)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < kHid * 16) {
-        int j = p / 16, k = p % 16;
-        net->W1[p] = k < kIn ? bf16_bits(master[kOffW1 + j * kIn + k]) : (unsigned short)0;
-    }
-    if (p < kHid * kHid)
-        net->W2[p] = bf16_bits(master[kOffW2 + p]);
-    if (p < kHid) {
-        net->b1[p] = bf16_value(bf16_bits(master[kOffB1 + p]));
-        net->b2[p] = bf16_value(bf16_bits(master[kOffB2 + p]));
-        net->W3[p] = bf16_value(bf16_bits(master[kOffW3 + p]));
-    }
-    if (p == 0)
-        net->b3 = bf16_value(bf16_bits(master[kOffB3]));
+    if (p < kHid * 16 && p % 16 >= kIn)
+        net->W1[p] = 0;
+    if (p < kParams)
+        pack_param(net, p, master[p]);
 }
 
 // ---------------------------------------------------------------------------
@@ -717,32 +917,47 @@ hipError_t launch_mlp_forward(const MlpPacked *net, const float *X, int64_t n, f
 
 size_t mlp_train_lds_bytes() { return sizeof(TrainLds); }
 
-hipError_t launch_mlp_train(const MlpPacked *net, const float *X, const float *y, int64_t n, float scale,
-                            float *part, int nblocks, hipStream_t s)
+// Blocks of the training kernel that fit on the device at once (the
+// cooperative launch needs every block resident).
+hipError_t mlp_train_max_blocks(int device, int *out)
 {
-    size_t lds = sizeof(TrainLds);
-    (void)hipFuncSetAttribute((const void *)mlp_train_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(mlp_train_kernel, dim3((unsigned)nblocks), dim3(256), lds, s, net, X, y, n, scale, part);
+    const size_t lds = sizeof(TrainLds);
+    hipError_t e =
+        hipFuncSetAttribute((const void *)mlp_train_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    int per_cu = 0, cus = 0;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mlp_train_kernel, kMlpThreads, lds)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess)
+        return e;
+    *out = per_cu * cus;
+    return hipSuccess;
+}
+
+hipError_t launch_mlp_sync_clear(unsigned long long *sync, unsigned int *fail, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_sync_clear_kernel, dim3(1), dim3(kMlpThreads), 0, s, sync, fail);
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_reduce(const float *part, int nblocks, float *grad, hipStream_t s)
+// run->steps optimizer steps (or, with apply = 0, one gradient evaluation)
+// on nblocks resident blocks; run is in device memory; *run->sync must hold
+// run->sync_base arrivals when the launch starts, and holds sync_base +
+// nblocks (2 steps - 1) after it.
+hipError_t launch_mlp_train(const TrainRun *run, int nblocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + 1 + 255) / 256), dim3(256), 0, s, part, nblocks, grad);
-    return hipGetLastError();
-}
-
-hipError_t launch_mlp_adam(float *master, float *m, float *v, const float *grad, int64_t step, float lr,
-                           hipStream_t s)
-{
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, master, m, v, grad, step, lr,
-                       0.9f, 0.999f, 1e-8f);
-    return hipGetLastError();
+    const TrainRun *arg = run;
+    void *args[] = {&arg};
+    return hipLaunchCooperativeKernel((const void *)mlp_train_kernel, dim3((unsigned)nblocks), dim3(kMlpThreads),
+                                      args, (unsigned)sizeof(TrainLds), s);
 }
 
 hipError_t launch_mlp_pack(const float *master, MlpPacked *net, hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_pack_kernel, dim3((kHid * kHid + 255) / 256), dim3(256), 0, s, master, net);
+    hipLaunchKernelGGL(mlp_pack_kernel, dim3((kParams + kMlpThreads - 1) / kMlpThreads), dim3(kMlpThreads), 0, s,
+                       master, net);
     return hipGetLastError();
 }
 

@@ -115,6 +115,31 @@ def test_training_reduces_loss():
     assert rep["loss_last"] < 0.1 * rep["loss_first"]
 
 
+def test_training_is_deterministic():
+    """Training sums its block partials in a fixed order: the same run of
+    300 steps (two launches of the persistent training kernel) twice from the
+    same parameters gives bit-identical parameters and losses."""
+    print("case surrogate training determinism", flush=True)
+    wl = bunch.C1
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    out = []
+    with _ctx(wl.bunch.n, wl.depth, wl.dt) as ctx:
+        ctx.init_bunch(r, u, 0.0)
+        ctx.init_history_straight()
+        ctx.surrogate_set(bunch.surrogate_init(4), bunch.sigma_ref_of(r))
+        X, y = ctx.surrogate_samples_torch(1 << 15, seed=12)
+        for _ in range(2):
+            ctx.surrogate_set(bunch.surrogate_init(4), bunch.sigma_ref_of(r))
+            rep = ctx.surrogate_train_torch(X, y, steps=300, batch=1024, lr=3e-3, lr_final=1e-4)
+            out.append((ctx.surrogate_get(), rep))
+    (p0, r0), (p1, r1) = out
+    print(f"   loss {r0['loss_first']:.4e} -> {r0['loss_last']:.4e}; rerun {r1['loss_first']:.4e} -> "
+          f"{r1['loss_last']:.4e}", flush=True)
+    assert np.array_equal(p0, p1)
+    assert r0["loss_first"] == r1["loss_first"] and r0["loss_last"] == r1["loss_last"]
+    assert r0["loss_last"] < 0.5 * r0["loss_first"]
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_guess_never_changes_results(precision):
     """k* and the fields are bit-identical with the paper's bisection, the
