@@ -110,13 +110,51 @@ def train_surrogate(ctx, wl, r, epochs=2):
     return rep
 
 
+def gyrating_start(wl, r, u, epochs=2):
+    """The gyrating workload's starting state: the bunch stepped (FP64, the
+    paper's bisection) for depth + 20 steps from its straight history, so
+    that every stored slot lies on the curving paths, and the surrogate
+    trained on 2^23 pairs of that state.  Returns the history, proper
+    velocities and network."""
+    from paper_2605_05543_amd import surrogate
+    from paper_2605_05543_amd._lib import Context
+
+    ctx = Context(n=wl.bunch.n, depth=wl.depth, q=-bunch.E_CHARGE, m=bunch.M_ELECTRON, dt=wl.dt,
+                  ext_field=wl.ext_field, dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re)
+    ctx.init_bunch(r, u, 0.0)
+    ctx.init_history_straight()
+    spin = wl.depth + 20
+    done = 0
+    while done < spin:
+        k = min(128, spin - done)
+        ctx.step(k)
+        done += k
+        ctx.sync()
+        log(f"  spin-up: {done} of {spin} steps")
+    rn, un, _, _ = ctx.state()
+    sig = bunch.sigma_ref_of(rn)
+    ctx.surrogate_set(bunch.surrogate_init(0), sig)
+    count = 1 << 23
+    X, y = ctx.surrogate_samples_torch(count, seed=31)
+    rep = surrogate.train(ctx, [(X, y)], batch=8192, steps=epochs * (count // 8192))
+    rep["batch"] = 8192
+    log(f"  surrogate trained on {count} pairs of the gyrating state: loss {rep['loss_first']:.3e} -> "
+        f"{rep['loss_last']:.3e} in {rep['steps']} steps, {rep['seconds']:.2f} s")
+    T, w, v = ctx.history()
+    start = {"T": T, "w": w, "v": v, "u": un, "params": ctx.surrogate_get(), "sigma_ref": sig, "training": rep,
+             "spin_up_steps": spin}
+    ctx.close()
+    return start
+
+
 def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_log2=0, keep_fields=False,
-             stage2=None):
+             stage2=None, start=None):
     """Time one search mode on the workload: ``steps`` steps after
     ``warmup``, kernel times from HIP events.  With ``keep_fields`` the
     path's step fields at the initial state (all particles) are returned
     too, for the error check against the oracle; with ``stage2`` (c5) the
-    run continues with the handoff and Stage-II transport."""
+    run continues with the handoff and Stage-II transport; ``start`` (the
+    gyrating workload) is a stored state and trained network to begin from."""
     import torch
 
     from paper_2605_05543_amd._lib import Context
@@ -126,9 +164,20 @@ def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_lo
     ctx = Context(n=n, depth=wl.depth, q=-bunch.E_CHARGE, m=bunch.M_ELECTRON, dt=wl.dt, ext_field=wl.ext_field,
                   dipole_b0=wl.dipole_b0, dipole_re=wl.dipole_re, precision=precision,
                   guess=4 if guess == 4 else 0, guess_group_log2=group_log2)
-    ctx.init_bunch(r, u, 0.0)
-    ctx.init_history_straight()
-    train_rep = train_surrogate(ctx, wl, r, train_epochs) if guess == 1 else None
+
+    def initial_state():
+        if start:
+            ctx.set_history(start["T"], start["w"], start["v"], start["u"])
+        else:
+            ctx.init_bunch(r, u, 0.0)
+            ctx.init_history_straight()
+
+    initial_state()
+    train_rep = None
+    if guess == 1 and start:
+        ctx.surrogate_set(start["params"], start["sigma_ref"])
+    elif guess == 1:
+        train_rep = train_surrogate(ctx, wl, r, train_epochs)
     ctx.set_mode(precision, guess)
     if guess == 4:
         ctx.step(1)  # the first step bisects and fills the bracket cache
@@ -209,7 +258,10 @@ def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_lo
         ctx = None
     if keep_fields and ctx is not None:
         # the path's step fields at the initial state, in the timed launch shape
-        ctx.init_history_straight()
+        if start:
+            initial_state()
+        else:
+            ctx.init_history_straight()
         ctx.step(1)
         out["_fields"] = ctx.fields()
     if ctx is not None:
@@ -219,16 +271,21 @@ def run_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_lo
     return out
 
 
-def cpu_baseline(wl, r, u, target_seconds=15.0):
+def cpu_baseline(wl, r, u, target_seconds=15.0, start=None):
     """The oracle's rate on a bounded sample of the workload (fields at
-    seeded targets x all sources at the initial state), on all host threads
-    and on one.  Returns the record and the oracle's fields at the sample's
-    targets (for the GPU paths' error)."""
+    seeded targets x all sources at the initial state: the straight-line
+    history, or the stored state of the gyrating workload), on all host
+    threads and on one.  Returns the record and the oracle's fields at the
+    sample's targets (for the GPU paths' error)."""
     import oracle
 
     orc = oracle.get()
     n = wl.bunch.n
-    T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
+    if start:
+        T, w, v = start["T"], start["w"], start["v"]
+        r = np.ascontiguousarray(w[-1])
+    else:
+        T, w, v = orc.init_straight(r, u, wl.depth, wl.dt)
     threads = orc.max_threads()
     probe = bunch.target_subset(n, 4 * threads, 1001)  # every thread busy in the rate probe
     t0 = time.perf_counter()
@@ -289,7 +346,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c5", "c3g"],
+                    help="c3g: the C3 bunch gyrating in a 0.5 T field, timed from a curved history")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--train-epochs", type=int, default=2, help="passes over the surrogate's training pairs")
     ap.add_argument("--paths", default=None,
@@ -314,16 +372,20 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path (the pair sum would shard by "
               "targets, each GPU holding a replica of the history ring). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    wl = {"c1": bunch.C1, "c2": bunch.C2, "c3": bunch.C3, "c5": bunch.C5}[args.workload]
+    wl = {"c1": bunch.C1, "c2": bunch.C2, "c3": bunch.C3, "c5": bunch.C5, "c3g": bunch.C3G}[args.workload]
     c5 = wl is bunch.C5
+    gyro = wl is bunch.C3G
     paths = args.paths or ("fp64:bisect,mixed:mlp/12" if c5 else
+                           "fp64:bisect,mixed:mlp/12,mixed:mlp,fp64:mlp/12,fp64:mlp,mixed:ballistic,fp64:ballistic"
+                           if gyro else
                            "fp64:bisect,mixed:mlp/12,mixed:mlp,mixed:bisect,mixed:ballistic,fp64:ballistic,"
                            "fp64:previous")
     import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    r, u = bunch.gaussian_bunch(wl.bunch)
+    r, u = bunch.gyrating_bunch(wl) if gyro else bunch.gaussian_bunch(wl.bunch)
     log(f"workload {wl.name}: N={wl.bunch.n} D={wl.depth} dt={wl.dt} steps={args.steps} warmup={args.warmup}")
+    start = gyrating_start(wl, r, u, args.train_epochs) if gyro else None
     pmap = {"fp64": 0, "mixed": 1}
     gmap = {name: k for k, name in enumerate(GUESS_NAMES) if name}
     results = []
@@ -334,7 +396,7 @@ def main():
         st2 = ({"steps": args.transport_steps, "dt_max": 1e-7, "gyro_fraction": 1 / 32}
                if c5 and head_candidate else None)
         results.append(run_path(wl, r, u, pmap[p], gmap[g], args.steps, args.warmup, args.train_epochs, int(lg or 0),
-                                keep_fields=(k == 0 or head_candidate) and not st2, stage2=st2))
+                                keep_fields=(k == 0 or head_candidate or gyro) and not st2, stage2=st2, start=start))
     plain = results[0]
     # headline: the mixed-precision surrogate-guided path when it was run,
     # else the first mixed path, else the plain FP64 path
@@ -384,8 +446,14 @@ def main():
         line["error_vs_oracle"] = {"plain": c5_error(plain["_fields"])}
     if c5 and "stage2" in head:
         line["stage2"] = head.pop("stage2")
+    if gyro:
+        line["gyrating_start"] = {"spin_up_steps": start["spin_up_steps"], "surrogate_training": start["training"]}
+        # sign tests per pair of each path over the bisection's: what each
+        # guess saves in searching the curved histories
+        for x in results:
+            x["probes_vs_bisect"] = x["probes_per_pair"] / plain["probes_per_pair"]
     if not args.no_cpu and not c5:
-        rec, ref = cpu_baseline(wl, r, u)
+        rec, ref = cpu_baseline(wl, r, u, target_seconds=8.0 if gyro else 15.0, start=start)
         line["cpu_baseline"] = rec
         line["error_vs_oracle"] = {x["spec"]: error_vs_oracle(x["_fields"], ref) for x in results if "_fields" in x}
         log(f"  errors vs the oracle: {line['error_vs_oracle']}")

@@ -125,7 +125,21 @@ C3 = Workload("c3_n65536_d512_dipole",
 C5 = Workload("c5_n262144_d1024_dipole",
               BunchSpec(262144, (2e-3, 2e-3, 5e-3), 5.0, center=(3 * R_EARTH, 0.0, 0.0), seed=5),
               1024, 1e-13, 2000, ext_field=1)
-WORKLOADS = {w.name: w for w in (C1, C2, C3, C5)}
+# C3's bunch (N = 65536, sigma = 1 mm, 1 MeV) moving across a uniform-looking
+# 0.5 T field: a dipole of equatorial field 0.5 T at 1 m, the bunch centred
+# there with its momenta along +y (gyro-radius 9.5 mm, 2.9 mrad of turn per
+# 0.1 ps step).  Its history curves by 1.5 rad over the 512 stored steps once
+# stepping has refilled the ring (depth + 20 steps from the straight start).
+C3G = Workload("c3g_n65536_d512_gyrating_0.5T", BunchSpec(65536, (1e-3, 1e-3, 1e-3), 1.0, seed=3),
+               512, 1e-13, 500, ext_field=1, dipole_b0=0.5, dipole_re=1.0)
+WORKLOADS = {w.name: w for w in (C1, C2, C3, C5, C3G)}
+
+
+def gyrating_bunch(wl=C3G):
+    """(r, u) of the gyrating workload: the seeded bunch about +z turned so
+    that it moves along +y, centred at (dipole_re, 0, 0)."""
+    r, u = gaussian_bunch(wl.bunch)
+    return rotate_to_lab(r, u, math.pi / 2, math.pi / 2, center=(wl.dipole_re, 0.0, 0.0))
 
 
 def target_subset(n, count, seed):

@@ -19,11 +19,12 @@ from paper_2605_05543_amd import bunch  # noqa: E402
 
 
 def _fake_path(wl, r, u, precision, guess, steps, warmup, train_epochs=2, group_log2=0, keep_fields=False,
-               stage2=None):
+               stage2=None, start=None):
     spec = f"{['fp64', 'mixed'][precision]}:{bench.GUESS_NAMES[guess]}" + (f"/{group_log2}" if group_log2 else "")
     rate = {"fp64:bisect": 1.2e11, "fp64:ballistic": 1.35e11}.get(spec, 1.3e11)
     out = {"precision": ["fp64", "mixed"][precision], "guess": bench.GUESS_NAMES[guess], "spec": spec,
-           "pair_evals_per_s": rate, "ms_per_step": 35.7, "pair_kernel_ms": 35.5, "flops_per_pair": 182.9}
+           "pair_evals_per_s": rate, "ms_per_step": 35.7, "pair_kernel_ms": 35.5, "flops_per_pair": 182.9,
+           "probes_per_pair": 10.0 if guess == 0 else 7.0}
     if keep_fields:
         n = wl.bunch.n
         out["_fields"] = (np.ones((3, n)), np.ones((3, n)))
@@ -94,10 +95,38 @@ def test_cpu_baseline_record():
 def test_headline_error_reported(monkeypatch):
     """With the oracle leg, the line carries each kept path's field error
     against the oracle's fields at the baseline's targets."""
-    monkeypatch.setattr(bench, "cpu_baseline", lambda wl, r, u: (
+    monkeypatch.setattr(bench, "cpu_baseline", lambda wl, r, u, **kw: (
         {"value": 1.0, "unit": "pair-evals/s", "cores": 1, "kind": "oracle", "sample": "s"},
         (np.arange(4), np.ones((3, 4)), np.ones((3, 4)), np.ones(4), np.ones(4))))
     d = _run_main(monkeypatch, ["--paths", "fp64:bisect,mixed:mlp/12"])
     assert set(d["error_vs_oracle"]) == {"fp64:bisect", "mixed:mlp/12"}
     assert d["error_vs_oracle"]["mixed:mlp/12"]["E_max_over_rms"] == 0.0
     assert "_fields" not in json.dumps(d)
+
+
+def test_gyrating_workload_line(monkeypatch):
+    """The gyrating workload's line: its config, the stored start and each
+    path's sign tests against the bisection's."""
+    monkeypatch.setattr(bench, "gyrating_start", lambda wl, r, u, epochs=2: {
+        "spin_up_steps": wl.depth + 20, "training": {"steps": 1}})
+    d = _run_main(monkeypatch, ["--no-cpu", "--workload", "c3g", "--paths", "fp64:bisect,mixed:mlp/12"])
+    assert d["config"]["workload"] == bunch.C3G.name
+    assert d["gyrating_start"]["spin_up_steps"] == bunch.C3G.depth + 20
+    assert [x["probes_vs_bisect"] for x in d["paths"]] == [1.0, 0.7]
+
+
+def test_cpu_baseline_from_a_stored_history():
+    """From a stored history (the gyrating workload's start) the oracle leg
+    uses that history and its newest positions as targets: given the
+    straight-line history it reproduces the default leg's fields."""
+    import oracle
+
+    wl = bunch.C1
+    r, u = bunch.gaussian_bunch(wl.bunch)
+    T, w, v = oracle.get().init_straight(r, u, wl.depth, wl.dt)
+    _, (sub, E, B, _, _) = bench.cpu_baseline(wl, r, u, target_seconds=0.2)
+    _, (sub2, E2, B2, _, _) = bench.cpu_baseline(wl, None, None, target_seconds=0.2,
+                                                 start={"T": T, "w": w, "v": v})
+    common, i1, i2 = np.intersect1d(sub, sub2, return_indices=True)
+    assert len(common) > 0
+    assert np.array_equal(E[:, i1], E2[:, i2]) and np.array_equal(B[:, i1], B2[:, i2])
