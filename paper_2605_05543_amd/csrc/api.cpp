@@ -22,7 +22,8 @@ namespace empp {
 int pair_fp64_tile(int D);
 hipError_t launch_pair_fp64(const PairParams &p, hipStream_t stream, bool kstar, bool count);
 hipError_t launch_pair_mixed(const PairParams &p, hipStream_t stream, bool kstar, bool count);
-hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, double *E, double *B, hipStream_t s);
+hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, const int32_t *order, double *E,
+                               double *B, hipStream_t s);
 hipError_t launch_push(const PushParams &p, hipStream_t s);
 hipError_t launch_init_straight(double4 *rw, double4 *rv, double *T, const double *r, const double *u, int64_t N,
                                 int D, double t0, double dt, hipStream_t s);
@@ -756,6 +757,7 @@ empp_status empp_step(empp_ctx *ctx, int64_t nsteps)
         q.E = ctx->E();
         q.B = ctx->B();
         q.part = ctx->part();
+        q.order = p.order;
         q.nsplit = ctx->nsplit;
         q.N = N;
         q.D = ctx->cfg.depth;
@@ -846,7 +848,7 @@ static empp_status fields_dev_impl(empp_ctx *ctx, int64_t m, const double *x_dev
             Ec = (double *)obuf.ptr;
             Bc = Ec + 3 * mc;
         }
-        HIP_TRY(launch_merge_fields(ctx->part(), ctx->nsplit, mc, Ec, Bc, ctx->stream));
+        HIP_TRY(launch_merge_fields(ctx->part(), ctx->nsplit, mc, nullptr, Ec, Bc, ctx->stream));
         if (m > N) {
             for (int k = 0; k < 3; ++k) {
                 HIP_TRY(hipMemcpyAsync(E_dev + k * m + a0, Ec + k * mc, mc * sizeof(double), hipMemcpyDeviceToDevice,
@@ -921,7 +923,7 @@ empp_status empp_fields_at_dev_noalloc(empp_ctx *ctx, double t, int64_t m, const
                                                     : launch_pair_fp64(p, ctx->stream, kstar_dev != nullptr, ctx->counting);
     if (e != hipSuccess)
         return fail(EMPP_EDEVICE, "pair pass: %s", hipGetErrorString(e));
-    HIP_TRY(launch_merge_fields(p.part, ctx->nsplit, m, E_dev, B_dev, ctx->stream));
+    HIP_TRY(launch_merge_fields(p.part, ctx->nsplit, m, nullptr, E_dev, B_dev, ctx->stream));
     return EMPP_OK;
 }
 

@@ -96,7 +96,8 @@ struct PushParams {
     double *u;          // [3][N]
     double *E;          // [3][N] self-field of the step (output of the merge)
     double *B;
-    const double *part; // [nsplit][12][N]
+    const double *part; // [nsplit][12][N], in the pair launch's target order
+    const int32_t *order; // target order -> particle index
     int32_t nsplit;
     int64_t N;
     int32_t D;

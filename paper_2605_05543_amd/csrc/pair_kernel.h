@@ -14,8 +14,9 @@
 // the lanes of a wavefront probe nearby history slots.  Sums are kept per
 // target in registers: a plain partial merged into a compensated total
 // (Neumaier in FP64 every 32 sources, Knuth's two-sum in FP32 every 4);
-// source chunks (grid.y) write (sum, compensation) partials that the push
-// kernel merges in a fixed order, so results do not depend on scheduling.
+// source chunks write (sum, compensation) partials, in the launch's target
+// order, that the merge kernel adds in a fixed order (and maps to particle
+// indices), so results do not depend on scheduling.
 //
 // Every sign test is the FP64 test of the paper's bracket, in both
 // precisions: the bracket index is bit-identical across paths and search
@@ -739,7 +740,9 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
             neumaier(sum[k], comp[k], acc[k]);
     }
     if (active) {
-        double *out = p.part + (int64_t)split * 12 * p.m + tgt;
+        // partials in the launch's target order (consecutive threads write
+        // consecutive entries); the merge maps them to particle indices
+        double *out = p.part + (int64_t)split * 12 * p.m + a;
         for (int k = 0; k < 6; ++k) {
             out[k * p.m] = (double)sum[k];
             out[(6 + k) * p.m] = (double)comp[k];

@@ -20,8 +20,11 @@ __device__ inline double merge_partials(const double *part, int nsplit, int64_t 
 
 // One thread per (component, target): the six field components of a
 // target are merged by six threads, which keeps enough loads in flight
-// for the nsplit x 12 x m partials.
-__global__ void merge_fields_kernel(const double *part, int nsplit, int64_t m, double *E, double *B)
+// for the nsplit x 12 x m partials.  The partials are in the pair launch's
+// target order; order[a] (null: the identity) is the particle index that
+// target a's fields are written at.
+__global__ void merge_fields_kernel(const double *part, int nsplit, int64_t m, const int32_t *order, double *E,
+                                    double *B)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= 6 * m)
@@ -29,10 +32,11 @@ __global__ void merge_fields_kernel(const double *part, int nsplit, int64_t m, d
     const int k = (int)(idx / m);
     const int64_t a = idx - (int64_t)k * m;
     const double v = merge_partials(part, nsplit, m, k, a);
+    const int64_t t = order ? (int64_t)order[a] : a;
     if (k < 3)
-        E[k * m + a] = v;
+        E[k * m + t] = v;
     else
-        B[(k - 3) * m + a] = v;
+        B[(k - 3) * m + t] = v;
 }
 
 // Sec. 2.6: B = (mu0/4pi)(3 (M.rhat) rhat - M)/r^3 with M = M0 e_z, written
@@ -374,10 +378,11 @@ hipError_t launch_transport(const TransportParams &p, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, double *E, double *B, hipStream_t s)
+hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, const int32_t *order, double *E,
+                               double *B, hipStream_t s)
 {
     hipLaunchKernelGGL(merge_fields_kernel, dim3((unsigned)((6 * m + 255) / 256)), dim3(256), 0, s, part, nsplit,
-                       m, E, B);
+                       m, order, E, B);
     return hipGetLastError();
 }
 
@@ -385,7 +390,7 @@ hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, double
 hipError_t launch_push(const PushParams &p, hipStream_t s)
 {
     if (p.self_field) {
-        hipError_t e = launch_merge_fields(p.part, p.nsplit, p.N, p.E, p.B, s);
+        hipError_t e = launch_merge_fields(p.part, p.nsplit, p.N, p.order, p.E, p.B, s);
         if (e != hipSuccess)
             return e;
     }
