@@ -36,11 +36,13 @@ namespace empp {
 constexpr int kHalfRecs = 2048;
 
 // Sources searched in lockstep by a thread, per search mode (measured at
-// N = 65536, D = 512): two for the mixed path's straight-line guess, whose
-// short search leaves room for a second one in flight; one elsewhere, where
-// the second search's registers cost more than its overlap gains (FP64
-// warm start 31.3 ms with one, 37.2 with two, which spill).
-constexpr int lockstep_sources(bool mix, int guess) { return mix && guess == 2 ? 2 : 1; }
+// N = 65536, D = 512): two for the mixed path's straight-line and
+// surrogate guesses, whose short searches leave room for a second one in
+// flight (surrogate: 32.27 -> 31.87 ms); one elsewhere, where the second
+// search's registers cost more than its overlap gains (FP64 straight-line
+// guess 31.07 ms with one, 32.26 with two, which spill; the bisection, 126
+// VGPRs either way, 35.19 and 35.31).
+constexpr int lockstep_sources(bool mix, int guess) { return mix && (guess == 2 || guess == 1) ? 2 : 1; }
 
 // LDS buffers: two of 64 KiB (staging overlapped with the search) while a
 // staged tile fits in kHalfRecs records, else one sized to the tile
