@@ -22,6 +22,8 @@ namespace empp {
 int pair_fp64_tile(int D);
 hipError_t launch_pair_fp64(const PairParams &p, hipStream_t stream, bool kstar, bool count);
 hipError_t launch_pair_mixed(const PairParams &p, hipStream_t stream, bool kstar, bool count);
+hipError_t launch_lightcone_records(const double4 *ring_w, const double *T, int64_t N, int D, int head,
+                                    double4 *rec, hipStream_t s);
 hipError_t launch_merge_fields(const double *part, int nsplit, int64_t m, const int32_t *order, double *E,
                                double *B, hipStream_t s);
 hipError_t launch_push(const PushParams &p, hipStream_t s);
@@ -86,7 +88,7 @@ constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t ring_w, ring_v, T, u, E, B, part, err, counters, diag, order, pos, skey, st, ad, kc, kc_bytes, total;
+    uint64_t ring_w, ring_v, rec, T, u, E, B, part, err, counters, diag, order, pos, skey, st, ad, kc, kc_bytes, total;
 };
 
 int tile_for_depth(int D) { return pair_fp64_tile(D); }
@@ -170,6 +172,8 @@ Layout layout_for(const empp_config &c)
     };
     L.ring_w = take(N * D * sizeof(double4));
     L.ring_v = take(N * D * sizeof(double4));
+    // light-cone records of the present pass (lightcone_records_kernel)
+    L.rec = take(N * D * sizeof(double4));
     L.T = take(D * sizeof(double));
     L.u = take(3 * N * sizeof(double));
     L.E = take(3 * N * sizeof(double));
@@ -293,6 +297,7 @@ struct empp_ctx {
     Tp *at(uint64_t off) const { return reinterpret_cast<Tp *>(ws + off); }
     double4 *ring_w() const { return at<double4>(L.ring_w); }
     double4 *ring_v() const { return at<double4>(L.ring_v); }
+    double4 *rec() const { return at<double4>(L.rec); }
     double *T() const { return at<double>(L.T); }
     double *u() const { return at<double>(L.u); }
     double *E() const { return at<double>(L.E); }
@@ -362,6 +367,7 @@ PairParams pair_params(empp_ctx *ctx)
     PairParams p{};
     p.ring_w = ctx->ring_w();
     p.ring_v = ctx->ring_v();
+    p.rec = ctx->rec();
     p.T = ctx->T();
     p.n_src = ctx->cfg.n;
     p.D = ctx->cfg.depth;
@@ -486,13 +492,33 @@ hipError_t launch_guesses(empp_ctx *ctx, PairParams &p, float *G_pair = nullptr,
     });
 }
 
+// Whether the pair launch for p runs a search mode that stages the
+// precomputed light-cone records (the midpoint ablation and a cold warm
+// start run the bisection).
+bool pair_needs_records(const PairParams &p)
+{
+    if (p.recon == 1)
+        return false;
+    if (p.guess == EMPP_GUESS_PREVIOUS)
+        return !p.kc_cold;
+    return pass_uses_records(p.guess);
+}
+
 hipError_t launch_pair(empp_ctx *ctx, PairParams &p, bool kstar, float *G_pair = nullptr,
                        double3 *cent_pair = nullptr)
 {
     hipError_t eg = launch_guesses(ctx, p, G_pair, cent_pair);
     if (eg != hipSuccess)
         return eg;
+    // the pass's light-cone records (guided searches), then the pair kernel
+    // (timed together)
     return timed(ctx, 0, [&]() {
+        if (pair_needs_records(p)) {
+            hipError_t e = launch_lightcone_records(p.ring_w, p.T, p.n_src, p.D, p.head,
+                                                    const_cast<double4 *>(p.rec), ctx->stream);
+            if (e != hipSuccess)
+                return e;
+        }
         if (ctx->cfg.precision == EMPP_MIXED)
             return launch_pair_mixed(p, ctx->stream, kstar, ctx->counting);
         return launch_pair_fp64(p, ctx->stream, kstar, ctx->counting);
@@ -918,9 +944,14 @@ empp_status empp_fields_at_dev_noalloc(empp_ctx *ctx, double t, int64_t m, const
     p.m = m;
     p.kstar = kstar_dev;
     p.part = reinterpret_cast<double *>(ctx->scratch);
-    // launched directly: no timing events, no guess buffers
-    hipError_t e = ctx->cfg.precision == EMPP_MIXED ? launch_pair_mixed(p, ctx->stream, kstar_dev != nullptr, ctx->counting)
-                                                    : launch_pair_fp64(p, ctx->stream, kstar_dev != nullptr, ctx->counting);
+    // launched directly: no timing events, no guess buffers; the records
+    // live in the context's workspace
+    hipError_t e = hipSuccess;
+    if (pair_needs_records(p))
+        e = launch_lightcone_records(p.ring_w, p.T, p.n_src, p.D, p.head, const_cast<double4 *>(p.rec), ctx->stream);
+    if (e == hipSuccess)
+        e = ctx->cfg.precision == EMPP_MIXED ? launch_pair_mixed(p, ctx->stream, kstar_dev != nullptr, ctx->counting)
+                                             : launch_pair_fp64(p, ctx->stream, kstar_dev != nullptr, ctx->counting);
     if (e != hipSuccess)
         return fail(EMPP_EDEVICE, "pair pass: %s", hipGetErrorString(e));
     HIP_TRY(launch_merge_fields(p.part, ctx->nsplit, m, nullptr, E_dev, B_dev, ctx->stream));

@@ -39,6 +39,7 @@ constexpr int kMaxSplits = 1024;   // source chunks of one launch
 struct PairParams {
     const double4 *ring_w;
     const double4 *ring_v;
+    const double4 *rec;  // light-cone records [N][D], newest slot first (lightcone_records_kernel)
     const double *T;
     int64_t n_src;      // sources N
     int32_t D;
@@ -88,6 +89,13 @@ struct PairParams {
 };
 
 constexpr uint16_t kBracketBefore = 0xFFFF;
+
+// Search modes (pair-kernel template argument) whose pass stages the
+// precomputed light-cone records of lightcone_records_kernel (the guided
+// searches, 1-3, and the warm start, 4) rather than computing them from the
+// positions while staging (the bisection, 0, and the cache-filling
+// bisection, 5).
+__host__ __device__ constexpr bool pass_uses_records(int guess) { return guess >= 1 && guess <= 4; }
 
 struct PushParams {
     double4 *ring_w;

@@ -375,28 +375,41 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
         ph += ph < 0 ? D : 0;
         Ls[b] = kC_LIGHT * (tnow - p.T[ph]);
     }
-    // Tile records are prefetched into registers one tile ahead (the first
-    // two records of each thread), so their HBM/L2 latency overlaps the
-    // previous tile's work; deeper histories load the rest in place.
     // Record q of a tile: source q / D (q < TS D, TS <= 4), slot q % D.
+    // The guided searches stage the pass's records written by
+    // lightcone_records_kernel (the tile's ns sources' D records are
+    // contiguous from p.rec[jt D]); the bisection, whose pass is bound by
+    // latency rather than issue, computes them from the positions while
+    // staging and saves the extra kernel.  What is loaded from HBM/L2 (a
+    // record or a position) is prefetched into registers one tile ahead (the
+    // first two of each thread), so its latency overlaps the previous tile's
+    // work; deeper histories load the rest in place.
+    constexpr bool kRecords = pass_uses_records(GUESS);
     auto src_of = [&](int q) { return (q >= D) + (q >= 2 * D) + (q >= 3 * D); };
     auto fetch = [&](int64_t jt, int ns, int q) -> double4 {
-        int s = src_of(q);
-        int b = q - s * D;
         double4 w = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (b < D && s < ns) {
-            int ph = p.head - b;
-            ph += ph < 0 ? D : 0;
-            w = p.ring_w[(jt + s) * D + ph];
+        if constexpr (kRecords) {
+            if (q < ns * D)
+                w = p.rec[jt * D + q];
+        } else {
+            const int s = src_of(q);
+            const int b = q - s * D;
+            if (b < D && s < ns) {
+                int ph = p.head - b;
+                ph += ph < 0 ? D : 0;
+                w = p.ring_w[(jt + s) * D + ph];
+            }
         }
         return w;
     };
     auto put = [&](int bi, int it_tile, int ns, int q, double4 w) {
-        int s = src_of(q);
-        int b = q - s * D;
-        if (b < D && s < ns) {
-            const double4 rec = lightcone_record(read_wn(it_tile, s), w, Ls[b]);
-            double2 *xy = halves + bi * 2 * hrec + s * D + b;
+        if (q < ns * D) {
+            double4 rec = w;
+            if constexpr (!kRecords) {
+                const int s = src_of(q);
+                rec = lightcone_record(read_wn(it_tile, s), w, Ls[q - s * D]);
+            }
+            double2 *xy = halves + bi * 2 * hrec + q;
             xy[0] = make_double2(rec.x, rec.y);
             xy[hrec] = make_double2(rec.z, rec.w);
         }
@@ -419,12 +432,8 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
         }
         put(bi, it_tile, ns, tid, r0);
         put(bi, it_tile, ns, tid + kBlockFp64, r1);
-        for (int q = tid + 2 * kBlockFp64; q < ns * D; q += kBlockFp64) {
-            int s = q / D, b = q - (q / D) * D;
-            int ph = p.head - b;
-            ph += ph < 0 ? D : 0;
-            put(bi, it_tile, ns, q, p.ring_w[(jt + s) * D + ph]);
-        }
+        for (int q = tid + 2 * kBlockFp64; q < ns * D; q += kBlockFp64)
+            put(bi, it_tile, ns, q, fetch(jt, ns, q));
     };
     auto tile_size = [&](int64_t jt) { return (int)((j1 - jt) < TS ? (j1 - jt) : TS); };
     double4 pf0 = make_double4(0.0, 0.0, 0.0, 0.0), pf1 = pf0;

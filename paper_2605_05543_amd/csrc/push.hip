@@ -3,8 +3,38 @@
 // arXiv 2605.05543), the straight-line prior history, layout conversions
 // and bunch diagnostics (Secs. 2.5, 2.7).
 #include "empp_dev.h"
+#include "pair_common.h"
 
 namespace empp {
+
+// Light-cone records of every (source j, slot b) at the present time T[head]
+// (b = 0 the newest slot): rec[j D + b] = {-2 D, L^2 - |D|^2} with
+// D = w_n - w_b and L = c (T[head] - T_b), the per-sample part of the split
+// sign test (lightcone_record).  Written once per pair pass, so that the
+// pair kernels' target blocks stage them instead of each recomputing them.
+__global__ void lightcone_records_kernel(const double4 *ring_w, const double *T, int64_t N, int D, int head,
+                                         double4 *rec)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N * (int64_t)D)
+        return;
+    const int64_t j = q / D;
+    const int b = (int)(q - j * D);
+    int ph = head - b;
+    ph += ph < 0 ? D : 0;
+    const double L = kC_LIGHT * (T[head] - T[ph]);
+    const double4 wn = ring_w[j * D + head];
+    rec[q] = lightcone_record(make_double4(wn.x, wn.y, wn.z, 0.0), ring_w[j * D + ph], L);
+}
+
+hipError_t launch_lightcone_records(const double4 *ring_w, const double *T, int64_t N, int D, int head,
+                                    double4 *rec, hipStream_t s)
+{
+    const int64_t n = N * (int64_t)D;
+    hipLaunchKernelGGL(lightcone_records_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ring_w, T, N, D,
+                       head, rec);
+    return hipGetLastError();
+}
 
 // Merge nsplit (sum, comp) partials of one component in split order.
 __device__ inline double merge_partials(const double *part, int nsplit, int64_t m, int k, int64_t a)

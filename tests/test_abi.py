@@ -37,9 +37,11 @@ def test_workspace_size_and_validation():
 
     cfg = _lib.Config(n=65536, depth=512, q=-1.602176634e-19, m=9.1093837015e-31, dt=1e-13)
     nbytes = _lib.empp_workspace_size(cfg)
-    ring = 65536 * 512 * 32 * 2
-    # the ring plus the per-chunk partials (at most 128 chunks x 12 doubles
-    # per target) and small per-particle arrays
+    # the two rings (positions, velocities) and the pass's light-cone
+    # records, 32 bytes per (particle, slot) each, plus the per-chunk
+    # partials (at most 128 chunks x 12 doubles per target) and small
+    # per-particle arrays
+    ring = 65536 * 512 * 32 * 3
     partials = 128 * 12 * 65536 * 8
     assert ring + partials <= nbytes < ring + partials + 64 * 2**20
     # the warm-start cache adds N*N uint16 brackets
