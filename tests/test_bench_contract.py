@@ -70,6 +70,19 @@ def test_line_has_the_contract_fields(monkeypatch):
         assert rf["hbm_bytes_per_pair"] == rf["traffic"] / (n * (n - 1))
 
 
+def test_line_without_the_plain_path(monkeypatch):
+    # no plain FP64 path among those run: no speedup over it is claimed, and
+    # the roofline names the kernel it was taken from
+    d = _run_main(monkeypatch, ["--no-cpu", "--paths", "mixed:mlp/12,fp64:ballistic"])
+    assert d["value"] == 1.3e11 and d["speedup_vs_plain_fp64"] is None
+    assert d["roofline"]["kernel"] == "pair kernel of the mixed:mlp/12 path"
+    d = _run_main(monkeypatch, ["--no-cpu", "--paths", "fp64:ballistic,fp64:bisect"])
+    # without a mixed path the plain one is the headline
+    assert d["roofline"]["kernel"].startswith("pair_fp64_kernel (plain")
+    assert d["value"] == 1.2e11 and d["speedup_vs_plain_fp64"] == 1.0
+    assert abs(d["speedup_vs_ballistic"] - 1.2 / 1.35) < 1e-12
+
+
 def test_several_gpus_are_refused(monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py", "--gpus", "2"])
     with pytest.raises(SystemExit) as ei:
