@@ -6,10 +6,10 @@
 
 namespace empp {
 
-template <bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID = false>
+template <bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID = false, int NIT = 0>
 __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
 {
-    pair_body<false, KSTAR, COUNT, GUESS, S, ADAPT, MID>(p);
+    pair_body<false, KSTAR, COUNT, GUESS, S, ADAPT, MID, NIT>(p);
 }
 
 // Sources per staged LDS tile (used to size the source chunks).
@@ -19,15 +19,30 @@ namespace {
 
 // One launch of a kernel instantiation: S sources per lockstep group,
 // staged / S groups per staged LDS tile.
-template <bool K, bool C, int G, int S, bool A, bool MID = false>
+template <bool K, bool C, int G, int S, bool A, bool MID = false, int NIT = 0>
 void launch_one(PairParams p, int staged, size_t lds, dim3 grid, hipStream_t stream)
 {
     p.tile = S;
     p.groups = staged / S;
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, C, G, S, A, MID>,
+        (void)hipFuncSetAttribute((const void *)pair_fp64_kernel<K, C, G, S, A, MID, NIT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S, A, MID>), grid, dim3(kBlockFp64), lds, stream, p);
+    hipLaunchKernelGGL((pair_fp64_kernel<K, C, G, S, A, MID, NIT>), grid, dim3(kBlockFp64), lds, stream, p);
+}
+
+// The plain bisection with its halvings unrolled for the launch's depth
+// (the fields path: no bracket output, no counters, fixed step) where the
+// tiles are double-buffered (D <= 2048); deeper histories loop.
+void launch_plain(const PairParams &p, int staged, size_t lds, dim3 grid, hipStream_t stream)
+{
+    switch (p.nbuf == 2 ? p.nit : 0) {
+#define EMPP_NIT(N) \
+    case N: launch_one<false, false, 0, 1, false, false, N>(p, staged, lds, grid, stream); return;
+        EMPP_NIT(1) EMPP_NIT(2) EMPP_NIT(3) EMPP_NIT(4) EMPP_NIT(5) EMPP_NIT(6)
+        EMPP_NIT(7) EMPP_NIT(8) EMPP_NIT(9) EMPP_NIT(10) EMPP_NIT(11)
+#undef EMPP_NIT
+    default: launch_one<false, false, 0, 1, false>(p, staged, lds, grid, stream);
+    }
 }
 
 // The lockstep width the search mode measured fastest with, where a staged
@@ -98,8 +113,13 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
         if (count) EMPP_MODE(false, true, 1, false); else EMPP_MODE(false, false, 1, false);
     } else if (p.guess == 2) {
         if (count) EMPP_BY_ADAPT(true, 2); else EMPP_BY_ADAPT(false, 2);
+    } else if (count) {
+        EMPP_BY_ADAPT(true, 0);
+    } else if (p.ad) {
+        EMPP_MODE(false, false, 0, true);
     } else {
-        if (count) EMPP_BY_ADAPT(true, 0); else EMPP_BY_ADAPT(false, 0);
+        static_assert(lockstep_sources(false, 0) == 1, "the plain bisection searches one source at a time");
+        launch_plain(p, staged, lds, grid, stream);
     }
 #undef EMPP_BY_ADAPT
 #undef EMPP_MODE

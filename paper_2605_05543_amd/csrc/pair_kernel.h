@@ -263,7 +263,10 @@ __device__ __forceinline__ bool lw_pair_mixed(double L1d, MixedPair q, bool befo
 
 }  // namespace
 
-template <bool MIX, bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID>
+// NIT: 0, or the number of bisection halvings of the launch's depth,
+// ceil(log2(D - 1)), for an unrolled bisection (GUESS 0, double-buffered
+// tiles: D <= 2048).
+template <bool MIX, bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID, int NIT = 0>
 __device__ __forceinline__ void pair_body(const PairParams &p)
 {
     extern __shared__ double4 lds[];
@@ -305,6 +308,7 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
         }
     }
     static_assert(!MIX || (!ADAPT && !MID && GUESS <= 3), "mixed precision: fixed step, no warm start");
+    static_assert(NIT == 0 || (GUESS == 0 && NIT <= 11), "an unrolled bisection has at most 11 halvings");
     // field sums: FP64 with Neumaier compensation, or FP32 with two-sum
     using Real = std::conditional_t<MIX, float, double>;
     Real sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
@@ -326,7 +330,9 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     // bank groups as with 32-byte records.  With two buffers the distance is
     // the fixed kHalfRecs, so a probe's two reads share one address (the
     // second one at an immediate offset).
-    const int nbuf = p.nbuf;
+    // (kernels with an unrolled bisection are launched for double-buffered
+    // tiles only)
+    const int nbuf = NIT > 0 ? 2 : p.nbuf;
     // A staged tile holds G groups of S sources; the S sources of a group
     // are searched in lockstep, and one barrier per staged tile serves all
     // its groups.
@@ -611,22 +617,40 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
 #pragma unroll
                     for (int s = 0; s < S; ++s)
                         any = any || (inside[s] && valid[s]);
-                    // halving widths depend on D only: uniform across lanes
-                    auto halve = [&](auto zl_off) {
-                        for (int n = D - 1; n > 1;) {
-                            const int half = n >> 1;
-                            const uint32_t hb = (uint32_t)half * (uint32_t)sizeof(double2);
+                    // one halving of width n: probe xb + floor(n / 2)
+                    auto probe = [&](int half, auto zl_off) {
+                        const uint32_t hb = (uint32_t)half * (uint32_t)sizeof(double2);
 #pragma unroll
-                            for (int s = 0; s < S; ++s) {
-                                const uint32_t mo = xo[s] + hb;
-                                typedef double dv2 __attribute__((ext_vector_type(2)));
-                                const dv2 va = *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)mo;
-                                const dv2 vb =
-                                    *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)(mo + (uint32_t)zl_off);
-                                const double4 rec = make_double4(va.x, va.y, vb.x, vb.y);
-                                xo[s] = inside_cone(s, rec) ? xo[s] : mo;
+                        for (int s = 0; s < S; ++s) {
+                            const uint32_t mo = xo[s] + hb;
+                            typedef double dv2 __attribute__((ext_vector_type(2)));
+                            const dv2 va = *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)mo;
+                            const dv2 vb =
+                                *(const __attribute__((address_space(3))) dv2 *)(uintptr_t)(mo + (uint32_t)zl_off);
+                            const double4 rec = make_double4(va.x, va.y, vb.x, vb.y);
+                            xo[s] = inside_cone(s, rec) ? xo[s] : mo;
+                        }
+                    };
+                    // The halving widths n = D - 1, n - floor(n / 2), ...
+                    // depend on D only (uniform across lanes).  With the
+                    // number of halvings known at compile time (NIT) the
+                    // sequence is unrolled: no loop compare or branch per
+                    // probe, the same probes as the loop.
+                    auto halve = [&](auto zl_off) {
+                        int n = D - 1;
+                        if constexpr (NIT > 0) {
+#pragma unroll
+                            for (int k = 0; k < NIT; ++k) {
+                                const int half = n >> 1;
+                                probe(half, zl_off);
+                                n -= half;
                             }
-                            n -= half;
+                        } else {
+                            while (n > 1) {
+                                const int half = n >> 1;
+                                probe(half, zl_off);
+                                n -= half;
+                            }
                         }
                     };
                     if (__any(any)) {

@@ -21,23 +21,39 @@ namespace empp {
 
 extern const bool kHaveMixed = true;
 
-template <bool KSTAR, bool COUNT, int GUESS, int S>
+template <bool KSTAR, bool COUNT, int GUESS, int S, int NIT = 0>
 __global__ __launch_bounds__(kBlockFp64, 4) void pair_mixed_kernel(PairParams p)
 {
-    pair_body<true, KSTAR, COUNT, GUESS, S, false, false>(p);
+    pair_body<true, KSTAR, COUNT, GUESS, S, false, false, NIT>(p);
 }
 
 namespace {
 
-template <bool K, bool C, int G, int S>
+template <bool K, bool C, int G, int S, int NIT = 0>
 void launch_one(PairParams p, int staged, size_t lds, dim3 grid, hipStream_t stream)
 {
     p.tile = S;
     p.groups = staged / S;
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)pair_mixed_kernel<K, C, G, S>,
+        (void)hipFuncSetAttribute((const void *)pair_mixed_kernel<K, C, G, S, NIT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((pair_mixed_kernel<K, C, G, S>), grid, dim3(kBlockFp64), lds, stream, p);
+    hipLaunchKernelGGL((pair_mixed_kernel<K, C, G, S, NIT>), grid, dim3(kBlockFp64), lds, stream, p);
+}
+
+// The bisection with its halvings unrolled for the launch's depth (no
+// bracket output, no counters) where the tiles are double-buffered
+// (D <= 2048); deeper histories loop.
+void launch_plain(const PairParams &p, int staged, size_t lds, dim3 grid, hipStream_t stream)
+{
+    static_assert(lockstep_sources(true, 0) == 1, "the bisection searches one source at a time");
+    switch (p.nbuf == 2 ? p.nit : 0) {
+#define EMPP_NIT(N) \
+    case N: launch_one<false, false, 0, 1, N>(p, staged, lds, grid, stream); return;
+        EMPP_NIT(1) EMPP_NIT(2) EMPP_NIT(3) EMPP_NIT(4) EMPP_NIT(5) EMPP_NIT(6)
+        EMPP_NIT(7) EMPP_NIT(8) EMPP_NIT(9) EMPP_NIT(10) EMPP_NIT(11)
+#undef EMPP_NIT
+    default: launch_one<false, false, 0, 1>(p, staged, lds, grid, stream);
+    }
 }
 
 template <bool K, bool C, int G>
@@ -73,7 +89,9 @@ hipError_t launch_pair_mixed(const PairParams &p0, hipStream_t stream, bool ksta
         else if (p.guess == 1) launch_mode<K, C, 1>(p, staged, lds, grid, stream);                           \
         else launch_mode<K, C, 0>(p, staged, lds, grid, stream);                                             \
     } while (0)
-    if (kstar) {
+    if (!kstar && !count && p.guess == 0) {
+        launch_plain(p, staged, lds, grid, stream);
+    } else if (kstar) {
         if (count) EMPP_BY_GUESS(true, true); else EMPP_BY_GUESS(true, false);
     } else {
         if (count) EMPP_BY_GUESS(false, true); else EMPP_BY_GUESS(false, false);
