@@ -6,7 +6,7 @@
 
 namespace empp {
 
-template <bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID = false, int NIT = 0>
+template <bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID = false, int NIT = -1>
 __global__ __launch_bounds__(kBlockFp64, 4) void pair_fp64_kernel(PairParams p)
 {
     pair_body<false, KSTAR, COUNT, GUESS, S, ADAPT, MID, NIT>(p);
@@ -19,7 +19,7 @@ namespace {
 
 // One launch of a kernel instantiation: S sources per lockstep group,
 // staged / S groups per staged LDS tile.
-template <bool K, bool C, int G, int S, bool A, bool MID = false, int NIT = 0>
+template <bool K, bool C, int G, int S, bool A, bool MID = false, int NIT = -1>
 void launch_one(PairParams p, int staged, size_t lds, dim3 grid, hipStream_t stream)
 {
     p.tile = S;
@@ -41,8 +41,22 @@ void launch_plain(const PairParams &p, int staged, size_t lds, dim3 grid, hipStr
         EMPP_NIT(1) EMPP_NIT(2) EMPP_NIT(3) EMPP_NIT(4) EMPP_NIT(5) EMPP_NIT(6)
         EMPP_NIT(7) EMPP_NIT(8) EMPP_NIT(9) EMPP_NIT(10) EMPP_NIT(11)
 #undef EMPP_NIT
-    default: launch_one<false, false, 0, 1, false>(p, staged, lds, grid, stream);
+    default: launch_one<false, false, 0, 1, false, false, -1>(p, staged, lds, grid, stream);
     }
+}
+
+// Guided fields launches over double-buffered tiles take the kernel with
+// the buffer count fixed at compile time.
+template <bool K, bool C, int G, int S, bool A>
+void launch_tiles(const PairParams &p, int staged, size_t lds, dim3 grid, hipStream_t stream)
+{
+    if constexpr (!K && !C && !A && G >= 1 && G <= 4) {
+        if (p.nbuf == 2) {
+            launch_one<K, C, G, S, A, false, 0>(p, staged, lds, grid, stream);
+            return;
+        }
+    }
+    launch_one<K, C, G, S, A>(p, staged, lds, grid, stream);
 }
 
 // The lockstep width the search mode measured fastest with, where a staged
@@ -52,11 +66,11 @@ void launch_mode(const PairParams &p, int staged, size_t lds, dim3 grid, hipStre
 {
     if constexpr (!A && lockstep_sources(false, G) == 2) {
         if (staged >= 2) {
-            launch_one<K, C, G, 2, A>(p, staged, lds, grid, stream);
+            launch_tiles<K, C, G, 2, A>(p, staged, lds, grid, stream);
             return;
         }
     }
-    launch_one<K, C, G, 1, A>(p, staged, lds, grid, stream);
+    launch_tiles<K, C, G, 1, A>(p, staged, lds, grid, stream);
 }
 
 }  // namespace

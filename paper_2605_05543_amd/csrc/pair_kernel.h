@@ -263,10 +263,10 @@ __device__ __forceinline__ bool lw_pair_mixed(double L1d, MixedPair q, bool befo
 
 }  // namespace
 
-// NIT: 0, or the number of bisection halvings of the launch's depth,
-// ceil(log2(D - 1)), for an unrolled bisection (GUESS 0, double-buffered
-// tiles: D <= 2048).
-template <bool MIX, bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID, int NIT = 0>
+// NIT: -1, the tile buffer count read at run time; 0, two buffers known at
+// compile time (D <= 2048); > 0, two buffers and the bisection unrolled for
+// NIT halvings, ceil(log2(D - 1)) of the launch's depth (GUESS 0).
+template <bool MIX, bool KSTAR, bool COUNT, int GUESS, int S, bool ADAPT, bool MID, int NIT = -1>
 __device__ __forceinline__ void pair_body(const PairParams &p)
 {
     extern __shared__ double4 lds[];
@@ -308,7 +308,7 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
         }
     }
     static_assert(!MIX || (!ADAPT && !MID && GUESS <= 3), "mixed precision: fixed step, no warm start");
-    static_assert(NIT == 0 || (GUESS == 0 && NIT <= 11), "an unrolled bisection has at most 11 halvings");
+    static_assert(NIT <= 0 || (GUESS == 0 && NIT <= 11), "an unrolled bisection has at most 11 halvings");
     // field sums: FP64 with Neumaier compensation, or FP32 with two-sum
     using Real = std::conditional_t<MIX, float, double>;
     Real sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
@@ -330,9 +330,7 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     // bank groups as with 32-byte records.  With two buffers the distance is
     // the fixed kHalfRecs, so a probe's two reads share one address (the
     // second one at an immediate offset).
-    // (kernels with an unrolled bisection are launched for double-buffered
-    // tiles only)
-    const int nbuf = NIT > 0 ? 2 : p.nbuf;
+    const int nbuf = NIT >= 0 ? 2 : p.nbuf;
     // A staged tile holds G groups of S sources; the S sources of a group
     // are searched in lockstep, and one barrier per staged tile serves all
     // its groups.

@@ -21,7 +21,7 @@ namespace empp {
 
 extern const bool kHaveMixed = true;
 
-template <bool KSTAR, bool COUNT, int GUESS, int S, int NIT = 0>
+template <bool KSTAR, bool COUNT, int GUESS, int S, int NIT = -1>
 __global__ __launch_bounds__(kBlockFp64, 4) void pair_mixed_kernel(PairParams p)
 {
     pair_body<true, KSTAR, COUNT, GUESS, S, false, false, NIT>(p);
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlockFp64, 4) void pair_mixed_kernel(PairParams p)
 
 namespace {
 
-template <bool K, bool C, int G, int S, int NIT = 0>
+template <bool K, bool C, int G, int S, int NIT = -1>
 void launch_one(PairParams p, int staged, size_t lds, dim3 grid, hipStream_t stream)
 {
     p.tile = S;
@@ -52,8 +52,22 @@ void launch_plain(const PairParams &p, int staged, size_t lds, dim3 grid, hipStr
         EMPP_NIT(1) EMPP_NIT(2) EMPP_NIT(3) EMPP_NIT(4) EMPP_NIT(5) EMPP_NIT(6)
         EMPP_NIT(7) EMPP_NIT(8) EMPP_NIT(9) EMPP_NIT(10) EMPP_NIT(11)
 #undef EMPP_NIT
-    default: launch_one<false, false, 0, 1>(p, staged, lds, grid, stream);
+    default: launch_one<false, false, 0, 1, -1>(p, staged, lds, grid, stream);
     }
+}
+
+// Guided fields launches over double-buffered tiles take the kernel with
+// the buffer count fixed at compile time.
+template <bool K, bool C, int G, int S>
+void launch_tiles(const PairParams &p, int staged, size_t lds, dim3 grid, hipStream_t stream)
+{
+    if constexpr (!K && !C && G >= 1) {
+        if (p.nbuf == 2) {
+            launch_one<K, C, G, S, 0>(p, staged, lds, grid, stream);
+            return;
+        }
+    }
+    launch_one<K, C, G, S>(p, staged, lds, grid, stream);
 }
 
 template <bool K, bool C, int G>
@@ -61,11 +75,11 @@ void launch_mode(const PairParams &p, int staged, size_t lds, dim3 grid, hipStre
 {
     if constexpr (lockstep_sources(true, G) == 2) {
         if (staged >= 2) {
-            launch_one<K, C, G, 2>(p, staged, lds, grid, stream);
+            launch_tiles<K, C, G, 2>(p, staged, lds, grid, stream);
             return;
         }
     }
-    launch_one<K, C, G, 1>(p, staged, lds, grid, stream);
+    launch_tiles<K, C, G, 1>(p, staged, lds, grid, stream);
 }
 
 }  // namespace
