@@ -56,11 +56,14 @@ constexpr int pair_nbuf(int D, int tile) { return (int64_t)tile * D <= kHalfRecs
 // wavefront and source, and the newest samples w_n of three tiles' sources.
 constexpr int kLineRecs = 2 * 2 * 4 + 2 * (kBlockFp64 / 64) * 4 / 4 + 3 * 4 * 2;
 
-constexpr size_t pair_lds_bytes(int D, int tile)
+// slot_table: the kernels with the tile buffer count fixed at compile time
+// (double-buffered tiles, D <= 2048) also keep, per logical slot, the byte
+// offsets of its ring row entry and of the next newer one.
+constexpr size_t pair_lds_bytes(int D, int tile, bool slot_table = false)
 {
     const size_t half = pair_nbuf(D, tile) == 2 ? kHalfRecs : (size_t)tile * D;
     return (size_t)pair_nbuf(D, tile) * 2 * half * sizeof(double2) + (size_t)((D + 1) & ~1) * sizeof(double) +
-           kLineRecs * sizeof(float4);
+           kLineRecs * sizeof(float4) + (slot_table ? (size_t)((D + 3) & ~3) * sizeof(uint32_t) : 0);
 }
 
 // Sources per staged LDS tile for a history depth: as many as fill a
@@ -69,6 +72,10 @@ constexpr int pair_staged_tile(int D) { return D <= kHalfRecs ? std::min(4, kHal
 
 static_assert(pair_lds_bytes(kMaxDepth, pair_staged_tile(kMaxDepth)) <= 160 * 1024,
               "the deepest history's tile, light distances and per-source data fit a CU's LDS");
+static_assert(pair_lds_bytes(kHalfRecs, pair_staged_tile(kHalfRecs), true) <= 160 * 1024,
+              "the deepest double-buffered tiles fit with the slot table");
+// its 16-bit byte offsets of 32-byte ring entries
+static_assert((kHalfRecs - 1) * 32 < 65536, "slot table offsets fit 16 bits");
 
 namespace {
 
@@ -345,6 +352,11 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     // (tile i in slot i % 3), as {x, y}, {z, -}: written two tiles ahead of
     // the tile's search, read when its records are staged and searched
     double2 *wnr = reinterpret_cast<double2 *>(gcorr + 2 * (kBlockFp64 / 64) * 4);
+    // slot table (NIT >= 0): for back offset b, the byte offset in a ring row
+    // of physical slot (head - b) mod D and, above 16 bits, of the next newer
+    // slot's (the bracket's two velocity records)
+    constexpr bool kSlotTable = NIT >= 0;
+    uint32_t *slot_off = reinterpret_cast<uint32_t *>(wnr + 3 * 4 * 2);
     auto write_wn = [&](int it_tile, int64_t jt, int ns) {
         if (tid < ns) {
             const double4 w = p.ring_w[(jt + tid) * D + p.head];
@@ -378,6 +390,10 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
         int ph = p.head - b;
         ph += ph < 0 ? D : 0;
         Ls[b] = kC_LIGHT * (tnow - p.T[ph]);
+        if constexpr (kSlotTable) {
+            const int ph2 = ph + 1 == D ? 0 : ph + 1;  // back offset b - 1 (read for b >= 1)
+            slot_off[b] = (uint32_t)ph * (uint32_t)sizeof(double4) | (uint32_t)ph2 * (uint32_t)sizeof(double4) << 16;
+        }
     }
     // Record q of a tile: source q / D (q < TS D, TS <= 4), slot q % D.
     // The guided searches stage the pass's records written by
@@ -537,14 +553,23 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
             // reconstruction, LW field and accumulation of tile source s
             auto load_v = [&](int s, int b, double4 &v1, double4 &v2) {
                 const int bb = b < 0 ? D - 1 : b;
-                int ph1 = p.head - bb;
-                ph1 += ph1 < 0 ? D : 0;
-                int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
+                uint32_t o1, o2;  // byte offsets of the two records in the source's row
+                if constexpr (kSlotTable) {
+                    const uint32_t w = slot_off[bb];
+                    o1 = w & 0xffffu;
+                    o2 = w >> 16;
+                } else {
+                    int ph1 = p.head - bb;
+                    ph1 += ph1 < 0 ? D : 0;
+                    const int ph2 = ph1 + 1 == D ? 0 : ph1 + 1;
+                    o1 = (uint32_t)ph1 * (uint32_t)sizeof(double4);
+                    o2 = (uint32_t)ph2 * (uint32_t)sizeof(double4);
+                }
                 // uniform row base plus 32-bit lane offsets
                 const char *row = reinterpret_cast<const char *>(p.ring_v + jj[s] * D);
-                v1 = *reinterpret_cast<const double4 *>(row + (uint32_t)ph1 * (uint32_t)sizeof(double4));
+                v1 = *reinterpret_cast<const double4 *>(row + o1);
                 // unused (inv_h = 0) out of history
-                v2 = *reinterpret_cast<const double4 *>(row + (uint32_t)ph2 * (uint32_t)sizeof(double4));
+                v2 = *reinterpret_cast<const double4 *>(row + o2);
             };
             auto finish = [&](int s, int b, double4 v1, double4 v2) {
                 const bool before = b < 0;

@@ -34,6 +34,8 @@ void launch_one(PairParams p, int staged, size_t lds, dim3 grid, hipStream_t str
 {
     p.tile = S;
     p.groups = staged / S;
+    if (NIT >= 0)
+        lds = pair_lds_bytes(p.D, staged, true);
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void *)pair_mixed_kernel<K, C, G, S, NIT>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
