@@ -50,6 +50,38 @@ def test_fields_at_wiggly(orc, n, depth, m, guess):
     assert_fields("wiggly", E, B, E0, B0, SE, SB)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_unrolled_bisection_every_halving_count(orc, precision):
+    """The fields launch (no bracket output) runs the bisection unrolled in a
+    kernel per number of halvings, ceil(log2(D - 1)) = 1 ... 11 for the
+    double-buffered depths; the bracket-output launch runs the halving loop.
+    Both must give bit-identical fields, within the tolerance of the
+    oracle's, at a depth of every halving count."""
+    dt = 1e-13
+    for depth in (3, 4, 6, 10, 18, 34, 66, 130, 258, 514, 1026, 2048):
+        n, m = 24, 70
+        print(f"case unrolled bisection D={depth} precision={precision}", flush=True)
+        # sources and targets spread over a third of the history's light
+        # distance: about a third of the pairs fall inside the history
+        L = bunch.C_LIGHT * dt * (depth - 1)
+        T, w, v = bunch.wiggly_history(n, depth, dt, beta=0.9, sigma=0.3 * L, accel_rel=0.1, seed=5 + depth)
+        rng = np.random.default_rng(depth)
+        x = w[-1][:, rng.integers(0, n, m)] + 0.3 * L * rng.standard_normal((3, m))
+        u = np.zeros((3, n))
+        E0, B0, k0, SE, SB = orc.fields(T, w, v, Q, T[-1], x, want_kstar=True, want_abs=True)
+        with _ctx(n, depth, dt, precision=precision) as ctx:
+            ctx.set_history(T, w, v, u)
+            E1, B1 = ctx.fields_at(T[-1], x)
+            E2, B2, k = ctx.fields_at(T[-1], x, want_kstar=True)
+        assert (k0 > 0).sum() > m * n // 4 and k0.max() == depth - 1
+        assert_kstar(f"D={depth}", k, k0)
+        assert np.array_equal(E1, E2) and np.array_equal(B1, B2), f"D={depth}: unrolled and looped bisection differ"
+        if precision == 0:
+            assert_fields(f"D={depth}", E1, B1, E0, B0, SE, SB)
+        else:
+            assert_mixed(f"D={depth} (mixed)", E1, B1, E0, B0, SE, SB)
+
+
 @pytest.mark.parametrize("guess", [0, 2])
 def test_c1_initial_all_targets(orc, guess):
     wl = bunch.C1
