@@ -33,17 +33,18 @@ void launch_one(PairParams p, int staged, size_t lds, dim3 grid, hipStream_t str
 }
 
 // The plain bisection with its halvings unrolled for the launch's depth
-// (the fields path: no bracket output, no counters, fixed step) where the
-// tiles are double-buffered (D <= 2048); deeper histories loop.
+// (the fields path: no bracket output, no counters; fixed or adaptive step)
+// where the tiles are double-buffered (D <= 2048); deeper histories loop.
+template <bool A>
 void launch_plain(const PairParams &p, int staged, size_t lds, dim3 grid, hipStream_t stream)
 {
     switch (p.nbuf == 2 ? p.nit : 0) {
 #define EMPP_NIT(N) \
-    case N: launch_one<false, false, 0, 1, false, false, N>(p, staged, lds, grid, stream); return;
+    case N: launch_one<false, false, 0, 1, A, false, N>(p, staged, lds, grid, stream); return;
         EMPP_NIT(1) EMPP_NIT(2) EMPP_NIT(3) EMPP_NIT(4) EMPP_NIT(5) EMPP_NIT(6)
         EMPP_NIT(7) EMPP_NIT(8) EMPP_NIT(9) EMPP_NIT(10) EMPP_NIT(11)
 #undef EMPP_NIT
-    default: launch_one<false, false, 0, 1, false, false, -1>(p, staged, lds, grid, stream);
+    default: launch_one<false, false, 0, 1, A, false, -1>(p, staged, lds, grid, stream);
     }
 }
 
@@ -131,11 +132,12 @@ hipError_t launch_pair_fp64(const PairParams &p0, hipStream_t stream, bool kstar
         if (count) EMPP_BY_ADAPT(true, 2); else EMPP_BY_ADAPT(false, 2);
     } else if (count) {
         EMPP_BY_ADAPT(true, 0);
-    } else if (p.ad) {
-        EMPP_MODE(false, false, 0, true);
     } else {
         static_assert(lockstep_sources(false, 0) == 1, "the plain bisection searches one source at a time");
-        launch_plain(p, staged, lds, grid, stream);
+        if (p.ad)
+            launch_plain<true>(p, staged, lds, grid, stream);
+        else
+            launch_plain<false>(p, staged, lds, grid, stream);
     }
 #undef EMPP_BY_ADAPT
 #undef EMPP_MODE
