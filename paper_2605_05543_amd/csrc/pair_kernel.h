@@ -13,7 +13,7 @@
 // the pair field evaluated.  Targets are visited in a spatial (Morton) order so that
 // the lanes of a wavefront probe nearby history slots.  Sums are kept per
 // target in registers: a plain partial merged into a compensated total
-// (Neumaier in FP64 every 32 sources, Knuth's two-sum in FP32 every 4);
+// (Neumaier in FP64 every 32 sources, Knuth's two-sum in FP32 every 8);
 // source chunks write (sum, compensation) partials, in the launch's target
 // order, that the merge kernel adds in a fixed order (and maps to particle
 // indices), so results do not depend on scheduling.
@@ -320,7 +320,7 @@ __device__ __forceinline__ void pair_body(const PairParams &p)
     using Real = std::conditional_t<MIX, float, double>;
     Real sum[6] = {0, 0, 0, 0, 0, 0}, comp[6] = {0, 0, 0, 0, 0, 0};
     Real acc[6] = {0, 0, 0, 0, 0, 0};
-    constexpr int kPlainRun = MIX ? 4 : 32;  // sources per plain partial
+    constexpr int kPlainRun = MIX ? 8 : 32;  // sources per plain partial
     const float kqf = (float)p.kq;
     int groups_in_acc = 0;
     int probes = 0, nbefore = 0, npairs = 0, nfall = 0, nresc = 0;
